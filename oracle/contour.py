@@ -1,0 +1,61 @@
+"""ECS contours q(x) and z(x) = int_0^x q(x') dx' (test infrastructure only).
+
+Sec. II, Eq. ECSintdef defines the complex coordinate z(x) = int_0^x q.
+Sec. IV gives the contours compared in the paper:
+
+* sharp:  q = 1 for |x| < r_s, q = exp(i theta_s) beyond;
+* SECS (Eq. qSECS): q = exp[i phi (|x| - r_s)/Dx_CS] for |x| > r_s with
+  Dx_CS = r_max - r_s.  The paper fixes the end angle phi = pi/4; here the end
+  angle is a parameter ``theta`` (pi/4 reproduces the paper);
+* off:    q = 1, z = x (plain SO-FFT).
+
+Readings:
+* r_max is the box edge b = L/2, so q reaches its end angle at the box edge.
+* Sharp contour at a tie |x| = r_s: the point is unscaled unless
+  |x| - r_s > 1e-9 h (h the grid step).  SECS is continuous there.
+"""
+import numpy as np
+
+SECS = "secs"
+SHARP = "sharp"
+OFF = "off"
+
+
+def q_of_x(x, kind, R0, rmax, theta, h):
+    """q(x) for the contour ``kind`` (Sec. IV)."""
+    x = np.asarray(x, dtype=float)
+    ax = np.abs(x)
+    q = np.ones(x.shape, dtype=complex)
+    if kind == OFF:
+        return q
+    if kind == SECS:
+        D = rmax - R0
+        out = ax > R0
+        q[out] = np.exp(1j * theta * (ax[out] - R0) / D)
+        return q
+    if kind == SHARP:
+        out = (ax - R0) > 1e-9 * h
+        q[out] = np.exp(1j * theta)
+        return q
+    raise ValueError(kind)
+
+
+def z_of_x(x, kind, R0, rmax, theta, h):
+    """z(x) = int_0^x q (Sec. II, Eq. ECSintdef), in closed form per contour."""
+    x = np.asarray(x, dtype=float)
+    ax = np.abs(x)
+    z = x.astype(complex)
+    if kind == OFF:
+        return z
+    if kind == SECS:
+        D = rmax - R0
+        out = ax > R0
+        s = (ax[out] - R0) / D
+        # int_{R0}^{|x|} exp(i theta (u - R0)/D) du = D/(i theta) (exp(i theta s) - 1)
+        z[out] = np.sign(x[out]) * (R0 + D / (1j * theta) * (np.exp(1j * theta * s) - 1.0))
+        return z
+    if kind == SHARP:
+        out = (ax - R0) > 1e-9 * h
+        z[out] = np.sign(x[out]) * (R0 + (ax[out] - R0) * np.exp(1j * theta))
+        return z
+    raise ValueError(kind)
