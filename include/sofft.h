@@ -1,0 +1,117 @@
+/*
+ * libsofft -- split-operator FFT propagation of the complex-scaled
+ * Schroedinger equation and FFT-preconditioned conjugate gradients for the
+ * stationary equation, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: V. V. Serov and T. A. Sergeeva, "Solution of the Schroedinger
+ * equation using exterior complex scaling and fast Fourier transform"
+ * (arXiv:1505.06707).  Sec. II defines the grid, the Fourier basis, the ECS
+ * contour and the split-operator step; Sec. III defines the stationary system
+ * and its FFT preconditioner.
+ *
+ * Conventions shared by every call:
+ *  - Grid (Sec. II, Eq. DVRgrid): on a box of length L per axis the nodes are
+ *    the cell centres x_j = -L/2 + h (j + 1/2), h = L/n, j = 0..n-1.
+ *  - Arrays are complex, interleaved (re, im), in device memory, row-major with
+ *    x the fast axis: psi[j_y * n_x + j_x].  Element type: double2 for
+ *    SOFFT_C128 plans, float2 for SOFFT_C64 plans.
+ *  - The values held are those of the scaled function psi~(x) = sqrt(q(x))
+ *    psi(z(x)) (Sec. II, Eq. psi_zx).
+ *  - Device buffers passed in are owned by the caller; the library never frees
+ *    or keeps them.  The plan owns its own small device tables (a few times n
+ *    elements per axis) and frees them in sofft_plan_destroy.
+ *  - Work is enqueued on the HIP stream given as `stream` (NULL = the default
+ *    stream) and is asynchronous unless the call writes to host memory.
+ *  - Errors: negative status codes; nothing has been enqueued when one is
+ *    returned, and sofft_last_error() (per thread) describes it.
+ *  - Plans are not thread-safe: one host thread at a time per plan.
+ */
+#ifndef SOFFT_H_
+#define SOFFT_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SOFFT_OK = 0,
+  SOFFT_EINVAL = -1,        /* bad argument (null pointer, size, range) */
+  SOFFT_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. grid length) */
+  SOFFT_EHIP = -3,          /* HIP runtime error */
+  SOFFT_ENOMEM = -4,        /* device allocation failed */
+  SOFFT_NOT_CONVERGED = 1,  /* solver hit maxit before rtol */
+  SOFFT_BREAKDOWN = 2       /* COCG breakdown that a restart did not cure */
+} sofft_status;
+
+typedef enum { SOFFT_C128 = 0, SOFFT_C64 = 1 } sofft_dtype;
+
+/* ECS contour q(x), Sec. IV.  SOFFT_SECS: q = exp(i theta (|x|-R0)/(L/2-R0))
+ * for |x| > R0 (Eq. qSECS with the end angle pi/4 replaced by theta).
+ * SOFFT_SHARP: q = exp(i theta) for |x| - R0 > 1e-9 h.  SOFFT_ECS_OFF: q = 1. */
+typedef enum { SOFFT_SECS = 0, SOFFT_SHARP = 1, SOFFT_ECS_OFF = 2 } sofft_contour;
+
+/* The problem statement of Sec. II/III: grid, ECS radius and angle, and the
+ * static part of U.  U(x, t) = V0(z(x)) + f(t) x with the soft-core Coulomb
+ * V0 = -charge / sqrt(z_x^2 [+ z_y^2] + a2) evaluated on the complex contour
+ * (principal branch) and the dipole term f(t) x at the real coordinate x
+ * (polarisation along x).  charge = 0 switches V0 off. */
+typedef struct {
+  int32_t ndim;      /* 1 or 2 */
+  int32_t dtype;     /* sofft_dtype of psi */
+  int64_t n[2];      /* nodes per axis: n[0] = n_x (fast), n[1] = n_y (2D only) */
+  double L[2];       /* box length per axis */
+  double R0[2];      /* ECS radius per axis, 0 < R0 < L/2 (ignored if contour off) */
+  double theta;      /* ECS angle, 0 < theta < pi/2 */
+  int32_t contour;   /* sofft_contour */
+  double charge;     /* soft-core strength (>= 0) */
+  double a2;         /* soft-core parameter a^2 (> 0 if charge > 0) */
+} sofft_problem;
+
+typedef struct sofft_plan sofft_plan;
+
+/* Message describing the last error on this host thread ("" if none). */
+const char* sofft_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t sofft_version(void);
+
+/* Build a plan: grid, momenta, contour tables q, z, the ECS remainder
+ * C = K_s - K_FD (Sec. II, Eqs. C_FD, Ks_FD, K_FD, periodic stencils) and FFT
+ * twiddles, and copy them to the current device.  Supported n per axis:
+ * 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024 (1D and 2D) and 2048,
+ * 4096 (1D only).  The scaled region may not cover the whole axis.
+ * Returns SOFFT_EINVAL / SOFFT_EUNSUPPORTED / SOFFT_ENOMEM / SOFFT_EHIP. */
+sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out);
+
+/* Free the plan and its device tables (after the work using it has finished). */
+sofft_status sofft_plan_destroy(sofft_plan* plan);
+
+/* Copy the n[axis] node coordinates x_j (Sec. II, Eq. DVRgrid) to host memory. */
+sofft_status sofft_grid_nodes(const sofft_plan* plan, int32_t axis, double* x_host);
+
+/* Number of nodes on the ECS strip of an axis, i.e. the nodes where the
+ * remainder C has a non-zero row (0 when ECS is off). */
+sofft_status sofft_strip_length(const sofft_plan* plan, int32_t axis, int64_t* m);
+
+/* Advance psi (device, in place, n_x [* n_y] elements) by nsteps split-operator
+ * steps of length dt (Sec. II):
+ *   psi <- F^-1 e^{-iK dt/2} F  e^{-iU dt/2}  e^{-iC dt}  e^{-iU dt/2}  F^-1 e^{-iK dt/2} F  psi
+ * with e^{-iC dt} by Crank-Nicolson, (1 + i dt C/2)^-1 (1 - i dt C/2), and U at
+ * the step midpoint: f_mid[s] = f(t0 + (s + 1/2) dt) is read from device memory
+ * (nsteps doubles; may be NULL when there is no field).  In 2D,
+ * K = (k_x^2 + k_y^2)/2 and e^{-iC dt} = CN(C_x) CN(C_y).  Neighbouring kinetic
+ * half-steps of consecutive steps are applied as one full step, which is exact.
+ * dt may be negative (backward propagation).  nsteps = 0 is a no-op. */
+sofft_status sofft_propagate(sofft_plan* plan, void* psi, double dt, int64_t nsteps,
+                             const double* f_mid, void* stream);
+
+/* ||psi||^2 = sum |psi_j|^2 accumulated in FP64 (blocking: waits for the stream). */
+sofft_status sofft_norm2(sofft_plan* plan, const void* psi, double* norm2_host, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOFFT_H_ */

@@ -1,0 +1,78 @@
+// Internal declarations shared by the host plan code and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cx.hpp"
+#include "../../include/sofft.h"
+
+namespace sofft {
+
+using zc = std::complex<double>;
+
+void set_error(const std::string& msg);
+
+#define SOFFT_HIP_TRY(expr)                                                        \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::sofft::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));       \
+      return SOFFT_EHIP;                                                           \
+    }                                                                              \
+  } while (0)
+
+// Device copy of a host vector; owned by the plan.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// One Cartesian axis of a problem: host tables (built from Sec. II) and their
+// device copies.
+struct Axis {
+  int64_t n = 0;
+  double L = 0, h = 0, R0 = 0, theta = 0;
+  int contour = SOFFT_SECS;
+  std::vector<double> x, xm, k;
+  std::vector<zc> q, qm, z;
+  std::vector<zc> cdn, cdg, cup;  // C_{j,j-1}, C_{j,j}, C_{j,j+1}
+  int64_t j0 = 0, m = 0;          // ECS strip: nodes (j0 + p) mod n, p < m
+
+  // Device tables that do not depend on dt (double and float copies).
+  DevBuf tw64, tw32, x_dev, z_dev, cstrip64;
+  // Tables that depend on dt.
+  double dt = 0;
+  bool have_dt = false;
+  int levels = 0;
+  DevBuf kin_full64, kin_half64, kin_full32, kin_half32;
+  DevBuf alpha64, gamma64, binv64, alpha32, gamma32, binv32;
+};
+
+struct Plan {
+  sofft_problem prob{};
+  Axis ax[2];
+  DevBuf partials;   // reduction scratch (norms)
+  std::vector<double> host_partials;
+};
+
+// Table builders (plan.hip).
+sofft_status build_axis(Axis& a, int64_t n, double L, double R0, double theta, int contour);
+sofft_status upload_static(Axis& a);
+sofft_status ensure_dt(Axis& a, double dt);
+void free_axis(Axis& a);
+sofft_status dev_upload(DevBuf& b, const void* host, size_t bytes);
+void dev_free(DevBuf& b);
+
+// Launchers (tdse.hip).
+sofft_status launch_propagate_1d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
+                                 hipStream_t s);
+sofft_status launch_propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
+                                 hipStream_t s);
+sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s);
+bool supported_length(int64_t n);
+
+}  // namespace sofft

@@ -1,0 +1,376 @@
+// Host side of a plan: the grid, momenta, ECS contour, the remainder C and the
+// Crank-Nicolson factor, FFT twiddles and kinetic phases (Sec. II), and their
+// device copies.
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace sofft {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+sofft_status dev_upload(DevBuf& b, const void* host, size_t bytes) {
+  if (b.p && b.bytes != bytes) dev_free(b);
+  if (!b.p) {
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      b.p = nullptr;
+      set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      return SOFFT_ENOMEM;
+    }
+    b.bytes = bytes;
+  }
+  SOFFT_HIP_TRY(hipMemcpy(b.p, host, bytes, hipMemcpyHostToDevice));
+  return SOFFT_OK;
+}
+
+void dev_free(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+bool supported_length(int64_t n) {
+  switch (n) {
+    case 16: case 32: case 48: case 64: case 96: case 128: case 192: case 256: case 384: case 512:
+    case 768: case 1024: case 2048: case 4096:
+      return true;
+    default:
+      return false;
+  }
+}
+
+// q(x) of the contour (Sec. IV): sharp rotation, smooth SECS (Eq. qSECS with
+// end angle theta at the box edge), or no scaling.
+static zc contour_q(double x, const Axis& a) {
+  const double ax = std::fabs(x);
+  switch (a.contour) {
+    case SOFFT_SECS:
+      if (ax > a.R0) return std::polar(1.0, a.theta * (ax - a.R0) / (a.L / 2 - a.R0));
+      return 1.0;
+    case SOFFT_SHARP:
+      if (ax - a.R0 > 1e-9 * a.h) return std::polar(1.0, a.theta);
+      return 1.0;
+    default:
+      return 1.0;
+  }
+}
+
+// z(x) = int_0^x q (Sec. II, Eq. ECSintdef) in closed form for each contour.
+static zc contour_z(double x, const Axis& a) {
+  const double ax = std::fabs(x), sg = x < 0 ? -1.0 : 1.0;
+  switch (a.contour) {
+    case SOFFT_SECS:
+      if (ax > a.R0) {
+        const double D = a.L / 2 - a.R0;
+        const double phi = a.theta * (ax - a.R0) / D;
+        // D/(i theta) (e^{i phi} - 1) = (D/theta) (sin phi + i (1 - cos phi))
+        return sg * zc(a.R0 + D / a.theta * std::sin(phi), D / a.theta * (1.0 - std::cos(phi)));
+      }
+      return x;
+    case SOFFT_SHARP:
+      if (ax - a.R0 > 1e-9 * a.h) return sg * (a.R0 + (ax - a.R0) * std::polar(1.0, a.theta));
+      return x;
+    default:
+      return x;
+  }
+}
+
+sofft_status build_axis(Axis& a, int64_t n, double L, double R0, double theta, int contour) {
+  a.n = n;
+  a.L = L;
+  a.h = L / double(n);
+  a.R0 = R0;
+  a.theta = theta;
+  a.contour = contour;
+  a.x.resize(n);
+  a.xm.resize(n);
+  a.k.resize(n);
+  a.q.resize(n);
+  a.qm.resize(n);
+  a.z.resize(n);
+  const double pi = 3.14159265358979323846;
+  for (int64_t j = 0; j < n; ++j) {
+    a.x[j] = -L / 2 + a.h * (double(j) + 0.5);   // cell centres
+    a.xm[j] = -L / 2 + a.h * double(j + 1);      // x_{j+1/2}; the last one is the box edge
+    const int64_t mm = j < n / 2 ? j : j - n;    // Eq. FFTbasis order, Nyquist negative
+    a.k[j] = 2 * pi * double(mm) / L;
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    a.q[j] = contour_q(a.x[j], a);
+    a.qm[j] = contour_q(a.xm[j], a);
+    a.z[j] = contour_z(a.x[j], a);
+  }
+  // C = K_s - K_FD from the three-point stencils of Eqs. Ks_FD and K_FD,
+  // periodic in j: the midpoint left of node 0 is the box edge (index n-1).
+  a.cdn.assign(n, 0.0);
+  a.cdg.assign(n, 0.0);
+  a.cup.assign(n, 0.0);
+  const double c = 1.0 / (2.0 * a.h * a.h);
+  std::vector<zc> qs(n);
+  for (int64_t j = 0; j < n; ++j) qs[j] = 1.0 / std::sqrt(a.q[j]);
+  for (int64_t j = 0; j < n; ++j) {
+    const int64_t jp = (j + 1) % n, jm = (j + n - 1) % n;
+    const zc qr = a.qm[j], ql = a.qm[jm];
+    a.cup[j] = -c * qs[j] * qs[jp] / qr + c;
+    a.cdn[j] = -c * qs[j] * qs[jm] / ql + c;
+    a.cdg[j] = c * (1.0 / a.q[j]) * (1.0 / qr + 1.0 / ql) - 2.0 * c;
+  }
+  // The strip: nodes whose row of C is non-zero.  It must be one cyclic run
+  // that leaves part of the axis unscaled.
+  std::vector<char> in(n, 0);
+  int64_t cnt = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    in[j] = (a.cdn[j] != 0.0 || a.cdg[j] != 0.0 || a.cup[j] != 0.0);
+    cnt += in[j];
+  }
+  a.m = cnt;
+  a.j0 = 0;
+  if (cnt > 0) {
+    if (cnt >= n - 1) {
+      set_error("the scaled region covers the whole axis; increase R0");
+      return SOFFT_EUNSUPPORTED;
+    }
+    int64_t starts = 0;
+    for (int64_t j = 0; j < n; ++j)
+      if (in[j] && !in[(j + n - 1) % n]) {
+        a.j0 = j;
+        ++starts;
+      }
+    if (starts != 1) {
+      set_error("the scaled region is not one contiguous run through the box edge");
+      return SOFFT_EUNSUPPORTED;
+    }
+  }
+  return SOFFT_OK;
+}
+
+template <typename T>
+static std::vector<cx<T>> to_cx(const std::vector<zc>& v) {
+  std::vector<cx<T>> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = {T(v[i].real()), T(v[i].imag())};
+  return o;
+}
+
+sofft_status upload_static(Axis& a) {
+  // Twiddles exp(-2 pi i u/n), evaluated in long double and rounded.
+  std::vector<zc> tw(a.n);
+  const long double pil = 3.141592653589793238462643383279502884L;
+  for (int64_t u = 0; u < a.n; ++u) {
+    const long double ang = 2.0L * pil * (long double)u / (long double)a.n;
+    tw[u] = zc(double(cosl(ang)), double(-sinl(ang)));
+  }
+  auto t64 = to_cx<double>(tw);
+  auto t32 = to_cx<float>(tw);
+  auto z64 = to_cx<double>(a.z);
+  sofft_status st;
+  if ((st = dev_upload(a.tw64, t64.data(), t64.size() * sizeof(t64[0]))) != SOFFT_OK) return st;
+  if ((st = dev_upload(a.tw32, t32.data(), t32.size() * sizeof(t32[0]))) != SOFFT_OK) return st;
+  if ((st = dev_upload(a.x_dev, a.x.data(), a.x.size() * sizeof(double))) != SOFFT_OK) return st;
+  if ((st = dev_upload(a.z_dev, z64.data(), z64.size() * sizeof(z64[0]))) != SOFFT_OK) return st;
+  return SOFFT_OK;
+}
+
+// Kinetic phases exp(-i k^2 dt/2)/n and exp(-i k^2 dt/4)/n (the 1/n of the
+// unscaled inverse FFT folded in), and the Crank-Nicolson system on the strip
+// prepared for parallel cyclic reduction.
+sofft_status ensure_dt(Axis& a, double dt) {
+  if (a.have_dt && a.dt == dt) return SOFFT_OK;
+  const int64_t n = a.n;
+  std::vector<zc> kf(n), kh(n);
+  for (int64_t j = 0; j < n; ++j) {
+    const long double e = (long double)a.k[j] * (long double)a.k[j] / 2.0L * (long double)dt;
+    kf[j] = zc(double(cosl(e) / n), double(-sinl(e) / n));
+    kh[j] = zc(double(cosl(e / 2) / n), double(-sinl(e / 2) / n));
+  }
+  sofft_status st;
+  {
+    auto f64 = to_cx<double>(kf), h64 = to_cx<double>(kh);
+    auto f32 = to_cx<float>(kf), h32 = to_cx<float>(kh);
+    if ((st = dev_upload(a.kin_full64, f64.data(), n * sizeof(f64[0]))) != SOFFT_OK) return st;
+    if ((st = dev_upload(a.kin_half64, h64.data(), n * sizeof(h64[0]))) != SOFFT_OK) return st;
+    if ((st = dev_upload(a.kin_full32, f32.data(), n * sizeof(f32[0]))) != SOFFT_OK) return st;
+    if ((st = dev_upload(a.kin_half32, h32.data(), n * sizeof(h32[0]))) != SOFFT_OK) return st;
+  }
+  // CN: y = (1 + i dt C/2)^-1 (1 - i dt C/2) v = 2 B^-1 v - v with B = 1 + i dt C/2.
+  // B restricted to the strip is tridiagonal: a_p u_{p-1} + b_p u_p + c_p u_{p+1}.
+  // PCR level l (stride s = 2^l) replaces row p by row p - alpha_p row(p-s)
+  // - gamma_p row(p+s); after ceil(log2 m) levels B is diagonal.
+  const int64_t m = a.m;
+  a.levels = 0;
+  if (m > 0) {
+    const zc ih(0.0, 0.5 * dt);
+    std::vector<zc> A(m), Bd(m), Cu(m);
+    for (int64_t p = 0; p < m; ++p) {
+      const int64_t j = (a.j0 + p) % n;
+      A[p] = p > 0 ? ih * a.cdn[j] : 0.0;
+      Bd[p] = 1.0 + ih * a.cdg[j];
+      Cu[p] = p + 1 < m ? ih * a.cup[j] : 0.0;
+    }
+    int levels = 0;
+    while ((int64_t(1) << levels) < m) ++levels;
+    std::vector<zc> al(size_t(levels) * m), ga(size_t(levels) * m);
+    for (int l = 0; l < levels; ++l) {
+      const int64_t s = int64_t(1) << l;
+      std::vector<zc> A2(m), B2(m), C2(m);
+      for (int64_t p = 0; p < m; ++p) {
+        const bool lo = p - s >= 0, hi = p + s < m;
+        const zc alpha = lo ? A[p] / Bd[p - s] : 0.0;
+        const zc gamma = hi ? Cu[p] / Bd[p + s] : 0.0;
+        al[size_t(l) * m + p] = alpha;
+        ga[size_t(l) * m + p] = gamma;
+        A2[p] = lo ? -alpha * A[p - s] : 0.0;
+        C2[p] = hi ? -gamma * Cu[p + s] : 0.0;
+        B2[p] = Bd[p] - (lo ? alpha * Cu[p - s] : 0.0) - (hi ? gamma * A[p + s] : 0.0);
+      }
+      A.swap(A2);
+      Bd.swap(B2);
+      Cu.swap(C2);
+    }
+    std::vector<zc> bi(m);
+    for (int64_t p = 0; p < m; ++p) bi[p] = 1.0 / Bd[p];
+    a.levels = levels;
+    std::vector<zc> dummy(1, 0.0);
+    const auto& alv = levels ? al : dummy;
+    const auto& gav = levels ? ga : dummy;
+    auto al64 = to_cx<double>(alv), ga64 = to_cx<double>(gav), bi64 = to_cx<double>(bi);
+    auto al32 = to_cx<float>(alv), ga32 = to_cx<float>(gav), bi32 = to_cx<float>(bi);
+    if ((st = dev_upload(a.alpha64, al64.data(), al64.size() * sizeof(al64[0]))) != SOFFT_OK) return st;
+    if ((st = dev_upload(a.gamma64, ga64.data(), ga64.size() * sizeof(ga64[0]))) != SOFFT_OK) return st;
+    if ((st = dev_upload(a.binv64, bi64.data(), bi64.size() * sizeof(bi64[0]))) != SOFFT_OK) return st;
+    if ((st = dev_upload(a.alpha32, al32.data(), al32.size() * sizeof(al32[0]))) != SOFFT_OK) return st;
+    if ((st = dev_upload(a.gamma32, ga32.data(), ga32.size() * sizeof(ga32[0]))) != SOFFT_OK) return st;
+    if ((st = dev_upload(a.binv32, bi32.data(), bi32.size() * sizeof(bi32[0]))) != SOFFT_OK) return st;
+  }
+  a.dt = dt;
+  a.have_dt = true;
+  return SOFFT_OK;
+}
+
+void free_axis(Axis& a) {
+  for (DevBuf* b : {&a.tw64, &a.tw32, &a.x_dev, &a.z_dev, &a.cstrip64, &a.kin_full64, &a.kin_half64,
+                    &a.kin_full32, &a.kin_half32, &a.alpha64, &a.gamma64, &a.binv64, &a.alpha32,
+                    &a.gamma32, &a.binv32})
+    dev_free(*b);
+}
+
+}  // namespace sofft
+
+using namespace sofft;
+
+struct sofft_plan : public Plan {};
+
+extern "C" {
+
+const char* sofft_last_error(void) { return g_err.c_str(); }
+
+int32_t sofft_version(void) { return 100; }
+
+sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
+  if (!prob || !out) {
+    set_error("null argument");
+    return SOFFT_EINVAL;
+  }
+  *out = nullptr;
+  const sofft_problem& p = *prob;
+  if (p.ndim != 1 && p.ndim != 2) {
+    set_error("ndim must be 1 or 2");
+    return SOFFT_EINVAL;
+  }
+  if (p.dtype != SOFFT_C128 && p.dtype != SOFFT_C64) {
+    set_error("dtype must be SOFFT_C128 or SOFFT_C64");
+    return SOFFT_EINVAL;
+  }
+  if (p.contour != SOFFT_SECS && p.contour != SOFFT_SHARP && p.contour != SOFFT_ECS_OFF) {
+    set_error("unknown contour");
+    return SOFFT_EINVAL;
+  }
+  if (p.contour != SOFFT_ECS_OFF && !(p.theta > 0 && p.theta < 1.5707963267948966)) {
+    set_error("theta must lie in (0, pi/2)");
+    return SOFFT_EINVAL;
+  }
+  if (!(p.charge >= 0) || (p.charge > 0 && !(p.a2 > 0))) {
+    set_error("charge must be >= 0 and a2 > 0 when charge > 0");
+    return SOFFT_EINVAL;
+  }
+  for (int d = 0; d < p.ndim; ++d) {
+    if (!supported_length(p.n[d]) || (p.ndim == 2 && p.n[d] > 1024)) {
+      set_error("unsupported grid length " + std::to_string(p.n[d]));
+      return SOFFT_EUNSUPPORTED;
+    }
+    if (!(p.L[d] > 0)) {
+      set_error("box length must be positive");
+      return SOFFT_EINVAL;
+    }
+    if (p.contour != SOFFT_ECS_OFF && !(p.R0[d] > 0 && p.R0[d] < p.L[d] / 2)) {
+      set_error("R0 must lie in (0, L/2)");
+      return SOFFT_EINVAL;
+    }
+  }
+  sofft_plan* pl = new sofft_plan();
+  pl->prob = p;
+  for (int d = 0; d < p.ndim; ++d) {
+    sofft_status st = build_axis(pl->ax[d], p.n[d], p.L[d], p.R0[d], p.theta, p.contour);
+    if (st == SOFFT_OK) st = upload_static(pl->ax[d]);
+    if (st != SOFFT_OK) {
+      for (int e = 0; e < 2; ++e) free_axis(pl->ax[e]);
+      delete pl;
+      return st;
+    }
+  }
+  *out = pl;
+  return SOFFT_OK;
+}
+
+sofft_status sofft_plan_destroy(sofft_plan* plan) {
+  if (!plan) return SOFFT_OK;
+  for (int d = 0; d < 2; ++d) free_axis(plan->ax[d]);
+  dev_free(plan->partials);
+  delete plan;
+  return SOFFT_OK;
+}
+
+sofft_status sofft_grid_nodes(const sofft_plan* plan, int32_t axis, double* x_host) {
+  if (!plan || !x_host || axis < 0 || axis >= plan->prob.ndim) {
+    set_error("bad argument to sofft_grid_nodes");
+    return SOFFT_EINVAL;
+  }
+  std::memcpy(x_host, plan->ax[axis].x.data(), plan->ax[axis].x.size() * sizeof(double));
+  return SOFFT_OK;
+}
+
+sofft_status sofft_strip_length(const sofft_plan* plan, int32_t axis, int64_t* m) {
+  if (!plan || !m || axis < 0 || axis >= plan->prob.ndim) {
+    set_error("bad argument to sofft_strip_length");
+    return SOFFT_EINVAL;
+  }
+  *m = plan->ax[axis].m;
+  return SOFFT_OK;
+}
+
+sofft_status sofft_propagate(sofft_plan* plan, void* psi, double dt, int64_t nsteps,
+                             const double* f_mid, void* stream) {
+  if (!plan || !psi || nsteps < 0 || !std::isfinite(dt)) {
+    set_error("bad argument to sofft_propagate");
+    return SOFFT_EINVAL;
+  }
+  if (nsteps == 0) return SOFFT_OK;
+  for (int d = 0; d < plan->prob.ndim; ++d) {
+    sofft_status st = ensure_dt(plan->ax[d], dt);
+    if (st != SOFFT_OK) return st;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return plan->prob.ndim == 1 ? launch_propagate_1d(*plan, psi, dt, nsteps, f_mid, s)
+                              : launch_propagate_2d(*plan, psi, dt, nsteps, f_mid, s);
+}
+
+sofft_status sofft_norm2(sofft_plan* plan, const void* psi, double* norm2_host, void* stream) {
+  if (!plan || !psi || !norm2_host) {
+    set_error("bad argument to sofft_norm2");
+    return SOFFT_EINVAL;
+  }
+  return launch_norm2(*plan, psi, norm2_host, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+"""Thin ctypes binding of libsofft (C ABI in include/sofft.h).
+
+Arguments are marshalled from torch device tensors (pointers, sizes) and the
+current torch stream; every step of the computation runs in the HIP library.
+There is no fallback: if the library is missing or the tensors are not on a
+GPU, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsofft.so")
+
+C128, C64 = 0, 1
+SECS, SHARP, ECS_OFF = 0, 1, 2
+
+_STATUS = {0: "SOFFT_OK", -1: "SOFFT_EINVAL", -2: "SOFFT_EUNSUPPORTED", -3: "SOFFT_EHIP",
+           -4: "SOFFT_ENOMEM", 1: "SOFFT_NOT_CONVERGED", 2: "SOFFT_BREAKDOWN"}
+
+
+class SofftError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 2),
+        ("L", ctypes.c_double * 2),
+        ("R0", ctypes.c_double * 2),
+        ("theta", ctypes.c_double),
+        ("contour", ctypes.c_int32),
+        ("charge", ctypes.c_double),
+        ("a2", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "sofft_last_error": (ctypes.c_char_p, []),
+    "sofft_version": (ctypes.c_int32, []),
+    "sofft_plan_create": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_void_p)]),
+    "sofft_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sofft_grid_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "sofft_strip_length": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "sofft_propagate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_norm2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_void_p]),
+}
+
+
+def exported_symbols():
+    """Names the binding expects the library to export."""
+    return list(_SIGS)
+
+
+def lib():
+    """Load libsofft.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code < 0:
+        raise SofftError(code, lib().sofft_last_error().decode())
+    return code
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A libsofft plan: grid, contour and potential of Sec. II, on the current device."""
+
+    def __init__(self, n, L, R0=None, theta=0.5, contour=SECS, charge=1.0, a2=2.0, dtype=C128):
+        n = list(n) if isinstance(n, (list, tuple)) else [n]
+        L = list(L) if isinstance(L, (list, tuple)) else [L] * len(n)
+        if R0 is None:
+            R0 = [l / 2 * 0.8 for l in L]
+        R0 = list(R0) if isinstance(R0, (list, tuple)) else [R0] * len(n)
+        p = Problem()
+        p.ndim = len(n)
+        p.dtype = dtype
+        for d in range(len(n)):
+            p.n[d] = int(n[d])
+            p.L[d] = float(L[d])
+            p.R0[d] = float(R0[d])
+        p.theta = float(theta)
+        p.contour = int(contour)
+        p.charge = float(charge)
+        p.a2 = float(a2)
+        self.problem = p
+        self.shape = tuple(int(v) for v in reversed(n))   # [ny][nx]
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        _check(lib().sofft_plan_create(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def numel(self):
+        return int(np.prod(self.shape))
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.complex128 if self.dtype == C128 else torch.complex64
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sofft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nodes(self, axis=0):
+        n = self.problem.n[axis]
+        out = np.empty(n, dtype=np.float64)
+        _check(lib().sofft_grid_nodes(self._h, axis, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def strip_length(self, axis=0):
+        m = ctypes.c_int64()
+        _check(lib().sofft_strip_length(self._h, axis, ctypes.byref(m)))
+        return m.value
+
+    def propagate(self, psi, dt, nsteps, f_mid=None, stream=None):
+        """Advance psi (device tensor, in place) by nsteps steps of dt."""
+        import torch
+        ptr = _dev_ptr(psi, self.torch_dtype, self.numel, "psi")
+        fptr = ctypes.c_void_p(0) if f_mid is None else _dev_ptr(f_mid, torch.float64, nsteps, "f_mid")
+        _check(lib().sofft_propagate(self._h, ptr, float(dt), int(nsteps), fptr, _stream(stream)))
+        return psi
+
+    def norm2(self, psi, stream=None):
+        ptr = _dev_ptr(psi, self.torch_dtype, self.numel, "psi")
+        out = ctypes.c_double()
+        _check(lib().sofft_norm2(self._h, ptr, ctypes.byref(out), _stream(stream)))
+        return out.value
