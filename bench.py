@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the SO-FFT + ECS hot path on one MI355X.
+
+One "step" is one split-operator time step (Sec. II: kinetic, potential and
+ECS/Crank-Nicolson factors) of the 2D workload: 1024 x 1024 grid, h = 0.2,
+complex128, soft-core potential with a 4-cycle dipole pulse, SECS on all four
+edges from 80% of the half-width, end angle 0.5.  ``value`` is grid points x
+steps per second with the state resident in HBM.  The JSON line also carries
+the roofline of the dominant kernel (HIP-event timed), the CPU oracle timed on
+a bounded sample, the complex64 mode, and the FFT-preconditioned COCG solve
+when the library provides it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point SO-FFT steps/s + PCG time-to-1e-8 residual, plain vs learned/batched"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gpu_tdse(sofft, wl, torch, dtype, steps, warmup, seed=1):
+    c = wl.TDSE_2D
+    plan = sofft.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=c.theta, charge=c.charge,
+                      a2=c.a2, dtype=dtype)
+    x = plan.nodes(0)
+    psi0 = wl.gaussian_2d(x, x, **wl.packet_params(seed))
+    cdt = np.complex128 if dtype == sofft.C128 else np.complex64
+    f_all = c.pulse.at_midpoints(0.0, c.dt, warmup + steps)
+    f_dev = torch.from_numpy(f_all).cuda()
+    psi = torch.from_numpy(psi0.astype(cdt)).cuda()
+    # warm-up steps (untimed), then the timed region
+    if warmup:
+        plan.propagate(psi, c.dt, warmup, f_dev[:warmup])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    plan.propagate(psi, c.dt, steps, f_dev[warmup:])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_s = e0.elapsed_time(e1) / 1e3
+    result = psi.clone()
+    # The same K steps again with every launch bracketed by HIP events on the
+    # library's stream, for the per-kernel durations of the roofline.
+    psi.copy_(torch.from_numpy(psi0.astype(cdt)).cuda())
+    plan.timing(True)
+    plan.propagate(psi, c.dt, steps, f_dev[warmup:])
+    kern = {name: plan.timing_read(k) for name, k in (("row_pass", sofft.KERNEL_ROW),
+                                                       ("column_pass", sofft.KERNEL_COL))}
+    plan.timing(False)
+    plan.close()
+    return dict(wall=wall, event_s=ev_s, kernels=kern, psi=result, npts=c.n * c.n)
+
+
+def cpu_baseline(wl, sample_steps, seed=1):
+    """The FP64 oracle on the host, a bounded sample of the same workload."""
+    from oracle import tdse as ot
+    c = wl.TDSE_2D
+    ax = ot.Axis(c.n, c.L, R0=c.R0, theta=c.theta)
+    prob = ot.Problem2D(ax, ax, Zc=c.charge, a2=c.a2)
+    psi0 = wl.gaussian_2d(ax.x, ax.x, **wl.packet_params(seed))
+    f = c.pulse.at_midpoints(0.0, c.dt, sample_steps)
+    prob.step(psi0, c.dt, f[0])          # factorisations and tables outside the timing
+    t0 = time.perf_counter()
+    prob.propagate(psi0, c.dt, f)
+    dt = time.perf_counter() - t0
+    return dict(value=c.n * c.n * sample_steps / dt, unit="grid-point-steps/s", cores=1, kind="oracle",
+                sample=f"{sample_steps} steps of the 1024^2 c128 workload (literal four-FFT step, "
+                       f"numpy pocketfft + scipy SuperLU, single thread) in {dt:.1f} s on "
+                       f"{platform.processor() or platform.machine()}, {os.cpu_count()} host threads visible")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-sample-steps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures a single GPU: this build runs on one MI355X and has no multi-GPU path "
+              "(the workload would shard by runs/energies; see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1505_06707_amd import sofft, workloads as wl
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    sofft.lib()
+
+    log(f"TDSE 2D 1024^2 c128: warmup {args.warmup}, timed {args.steps} steps")
+    r64 = gpu_tdse(sofft, wl, torch, sofft.C128, args.steps, args.warmup)
+    npts = r64["npts"]
+    value = npts * args.steps / r64["wall"]
+    ms_per_step = r64["wall"] / args.steps * 1e3
+    log(f"  {ms_per_step * 1e3:.1f} us/step, {value / 1e9:.2f} G grid-point-steps/s")
+
+    # roofline of the dominant kernel: algorithmic bytes = read + write of the state
+    # (2 x 16 B per grid point) per launch of a row or column pass
+    kern = r64["kernels"]
+    dom = max(kern, key=lambda k: kern[k][0])
+    tot_ms, cnt = kern[dom]
+    avg_s = tot_ms / cnt / 1e3
+    alg_bytes = 2 * 16 * npts
+    achieved = alg_bytes / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "avg_launch_us": avg_s * 1e6, "launches": cnt,
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "kernels_avg_us": {k: v[0] / v[1] * 1e3 for k, v in kern.items() if v[1]}}
+    log(f"  dominant kernel {dom}: {avg_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s "
+        f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)")
+
+    fp32 = None
+    if not args.no_fp32:
+        log("TDSE 2D 1024^2 c64")
+        r32 = gpu_tdse(sofft, wl, torch, sofft.C64, args.steps, args.warmup)
+        a = r64["psi"].cpu().numpy()
+        b = r32["psi"].cpu().numpy().astype(np.complex128)
+        err = float(np.linalg.norm(b - a) / np.linalg.norm(a))
+        fp32 = {"value": npts * args.steps / r32["wall"], "unit": "grid-point-steps/s",
+                "ms_per_step": r32["wall"] / args.steps * 1e3,
+                "rel_l2_vs_fp64_path": err, "steps": args.steps + args.warmup}
+        log(f"  c64: {fp32['ms_per_step'] * 1e3:.1f} us/step, rel L2 vs FP64 path {err:.2e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"CPU oracle sample: {args.cpu_sample_steps} steps")
+        cpu = cpu_baseline(wl, args.cpu_sample_steps)
+        log(f"  {cpu['value'] / 1e6:.2f} M grid-point-steps/s")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "tdse_2d_1024_c128", "grid": [1024, 1024], "h": 0.2, "dt": 0.05,
+                   "ecs": "SECS, R0 = 81.92 (80% of half-width), end angle 0.5",
+                   "potential": "soft-core a2=0.64 + dipole pulse E0=0.05 w=0.057 4 cycles",
+                   "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp32": fp32,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

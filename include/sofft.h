@@ -81,7 +81,8 @@ int32_t sofft_version(void);
  * C = K_s - K_FD (Sec. II, Eqs. C_FD, Ks_FD, K_FD, periodic stencils) and FFT
  * twiddles, and copy them to the current device.  Supported n per axis:
  * 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024 (1D and 2D) and 2048,
- * 4096 (1D only).  The scaled region may not cover the whole axis.
+ * 4096 (1D only).  The ECS strip (nodes where C is non-zero) may hold at most
+ * half of the nodes of an axis, and at most 256 nodes per axis in 2D.
  * Returns SOFFT_EINVAL / SOFFT_EUNSUPPORTED / SOFFT_ENOMEM / SOFFT_EHIP. */
 sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out);
 
@@ -109,6 +110,25 @@ sofft_status sofft_propagate(sofft_plan* plan, void* psi, double dt, int64_t nst
 
 /* ||psi||^2 = sum |psi_j|^2 accumulated in FP64 (blocking: waits for the stream). */
 sofft_status sofft_norm2(sofft_plan* plan, const void* psi, double* norm2_host, void* stream);
+
+/* Kernels whose launches can be timed (see sofft_timing_*). */
+typedef enum {
+  SOFFT_KERNEL_ROW = 0,   /* 2D row pass (x lines) of the propagation */
+  SOFFT_KERNEL_COL = 1,   /* 2D column pass (y lines) of the propagation */
+  SOFFT_KERNEL_1D = 2,    /* 1D whole-propagation kernel */
+  SOFFT_KERNEL_COUNT_ = 16
+} sofft_kernel;
+
+/* Measurement aid: while enabled, every launch of the plan's kernels is
+ * bracketed by a pair of HIP events on the launch stream.  Enabling clears the
+ * accumulated record.  Not for production use: event pairs add a small gap
+ * between launches. */
+sofft_status sofft_timing_enable(sofft_plan* plan, int32_t enable);
+
+/* Sum of the event-measured durations (milliseconds) and number of launches
+ * of one kernel kind since timing was enabled.  Blocks until the recorded
+ * events have completed. */
+sofft_status sofft_timing_read(sofft_plan* plan, int32_t kernel, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@
 #include <vector>
 
 #include "cx.hpp"
-#include "../../include/sofft.h"
+#include "sofft.h"
 
 namespace sofft {
 
@@ -52,11 +52,30 @@ struct Axis {
   DevBuf alpha64, gamma64, binv64, alpha32, gamma32, binv32;
 };
 
+// Optional per-launch event timing (measurement aid).
+struct Timing {
+  bool on = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double total_ms[SOFFT_KERNEL_COUNT_] = {};
+  int64_t count[SOFFT_KERNEL_COUNT_] = {};
+  sofft_status begin(int kind, hipStream_t s);
+  sofft_status end(hipStream_t s);
+  sofft_status drain();
+  void clear();
+  ~Timing();
+};
+
 struct Plan {
   sofft_problem prob{};
   Axis ax[2];
   DevBuf partials;   // reduction scratch (norms)
   std::vector<double> host_partials;
+  Timing timing;
 };
 
 // Table builders (plan.hip).

@@ -1,0 +1,208 @@
+// Stockham FFT along one "line" (a row or a column of the grid) with the
+// line spread over many threads, data in registers between stages and LDS
+// exchanges in between.
+//
+// A line of N = R0 * RR^K points (RR = 4 or 8) is owned by TPL = N/P threads; thread t holds
+// element t + TPL*s in register slot s (s < P).  This is the layout in which
+// rows and columns are loaded from and stored to HBM, in which the first stage
+// reads its inputs and in which the last stage leaves its outputs (natural
+// order).  Stage 0 has radix R0 (2, 3, 4, 6 or 8) and no twiddles; stages 1..K have
+// radix RR and run in a rolled loop with the stride NS = R0 RR^(s-1) as a
+// runtime value, so the code of a whole transform stays small.
+//
+// Stockham indexing for a stage of radix R and stride NS: butterfly j takes
+// elements j + m N/R (slots b + m P/R of thread t when j = t + TPL b),
+// multiplies input m by w^(m (j mod NS)) with w = exp(-+2 pi i/(NS R)), and
+// writes output m to element (j/NS) NS R + j mod NS + m NS.  The last stage has
+// NS R = N and writes back into the same slots.
+//
+// Forward = sum_j x_j exp(-2 pi i jk/N), inverse = sum_j x_j exp(+2 pi i jk/N);
+// neither is scaled.
+#pragma once
+#include "cx.hpp"
+
+namespace sofft {
+
+// N = R0 * RR^K with RR = 4 or 8; P points per thread (a multiple of R0 and
+// of RR).  PAD is the LDS padding period (one spare element per PAD), chosen so
+// that the stride-R0 writes of stage 0 do not collide in LDS banks; 0 means no
+// padding.  SOFFT_RADIX8 selects the radix-8 engine for power-of-two lengths.
+template <int N> struct Shape;
+#if defined(SOFFT_RADIX16)
+template <> struct Shape<16>   { static constexpr int P = 4,  R0 = 4,  RR = 4,  K = 1, PAD = 4; };
+template <> struct Shape<32>   { static constexpr int P = 16, R0 = 2,  RR = 16, K = 1, PAD = 2; };
+template <> struct Shape<64>   { static constexpr int P = 16, R0 = 4,  RR = 16, K = 1, PAD = 4; };
+template <> struct Shape<128>  { static constexpr int P = 16, R0 = 8,  RR = 16, K = 1, PAD = 8; };
+template <> struct Shape<256>  { static constexpr int P = 16, R0 = 16, RR = 16, K = 1, PAD = 16; };
+template <> struct Shape<512>  { static constexpr int P = 16, R0 = 2,  RR = 16, K = 2, PAD = 2; };
+template <> struct Shape<1024> { static constexpr int P = 16, R0 = 4,  RR = 16, K = 2, PAD = 4; };
+template <> struct Shape<2048> { static constexpr int P = 16, R0 = 8,  RR = 16, K = 2, PAD = 8; };
+template <> struct Shape<4096> { static constexpr int P = 16, R0 = 16, RR = 16, K = 2, PAD = 16; };
+#elif defined(SOFFT_RADIX8)
+template <> struct Shape<16>   { static constexpr int P = 8,  R0 = 2, RR = 8, K = 1, PAD = 2; };
+template <> struct Shape<32>   { static constexpr int P = 8,  R0 = 4, RR = 8, K = 1, PAD = 4; };
+template <> struct Shape<64>   { static constexpr int P = 8,  R0 = 8, RR = 8, K = 1, PAD = 8; };
+template <> struct Shape<128>  { static constexpr int P = 8,  R0 = 2, RR = 8, K = 2, PAD = 2; };
+template <> struct Shape<256>  { static constexpr int P = 8,  R0 = 4, RR = 8, K = 2, PAD = 4; };
+template <> struct Shape<512>  { static constexpr int P = 8,  R0 = 8, RR = 8, K = 2, PAD = 8; };
+template <> struct Shape<1024> { static constexpr int P = 8,  R0 = 2, RR = 8, K = 3, PAD = 2; };
+template <> struct Shape<2048> { static constexpr int P = 8,  R0 = 4, RR = 8, K = 3, PAD = 4; };
+template <> struct Shape<4096> { static constexpr int P = 8,  R0 = 8, RR = 8, K = 3, PAD = 8; };
+#else
+template <> struct Shape<16>   { static constexpr int P = 4,  R0 = 4, RR = 4, K = 1, PAD = 4; };
+template <> struct Shape<32>   { static constexpr int P = 4,  R0 = 2, RR = 4, K = 2, PAD = 2; };
+template <> struct Shape<64>   { static constexpr int P = 4,  R0 = 4, RR = 4, K = 2, PAD = 4; };
+template <> struct Shape<128>  { static constexpr int P = 4,  R0 = 2, RR = 4, K = 3, PAD = 2; };
+template <> struct Shape<256>  { static constexpr int P = 4,  R0 = 4, RR = 4, K = 3, PAD = 4; };
+template <> struct Shape<512>  { static constexpr int P = 4,  R0 = 2, RR = 4, K = 4, PAD = 2; };
+template <> struct Shape<1024> { static constexpr int P = 4,  R0 = 4, RR = 4, K = 4, PAD = 4; };
+template <> struct Shape<2048> { static constexpr int P = 4,  R0 = 2, RR = 4, K = 5, PAD = 2; };
+template <> struct Shape<4096> { static constexpr int P = 4,  R0 = 4, RR = 4, K = 5, PAD = 4; };
+#endif
+template <> struct Shape<48>   { static constexpr int P = 12, R0 = 3, RR = 4, K = 2, PAD = 0; };
+template <> struct Shape<96>   { static constexpr int P = 12, R0 = 6, RR = 4, K = 2, PAD = 6; };
+template <> struct Shape<192>  { static constexpr int P = 12, R0 = 3, RR = 4, K = 3, PAD = 0; };
+template <> struct Shape<384>  { static constexpr int P = 12, R0 = 6, RR = 4, K = 3, PAD = 6; };
+template <> struct Shape<768>  { static constexpr int P = 12, R0 = 3, RR = 4, K = 4, PAD = 0; };
+
+// The same shape data at run time (host side), for table building.
+struct ShapeInfo {
+  int P, R0, RR, K;
+};
+template <int N>
+constexpr ShapeInfo shape_info_of() {
+  return {Shape<N>::P, Shape<N>::R0, Shape<N>::RR, Shape<N>::K};
+}
+inline ShapeInfo shape_info(long n) {
+  switch (n) {
+    case 16: return shape_info_of<16>();
+    case 32: return shape_info_of<32>();
+    case 48: return shape_info_of<48>();
+    case 64: return shape_info_of<64>();
+    case 96: return shape_info_of<96>();
+    case 128: return shape_info_of<128>();
+    case 192: return shape_info_of<192>();
+    case 256: return shape_info_of<256>();
+    case 384: return shape_info_of<384>();
+    case 512: return shape_info_of<512>();
+    case 768: return shape_info_of<768>();
+    case 1024: return shape_info_of<1024>();
+    case 2048: return shape_info_of<2048>();
+    case 4096: return shape_info_of<4096>();
+    default: return {0, 0, 0, 0};
+  }
+}
+
+// Twiddle tables, one per rolled stage s = 1..K (stride NS_s = R0 RR^(s-1)),
+// laid out contiguously so that the lanes of a wave read consecutive entries:
+// entry (s, m, k) = exp(-2 pi i m k N/(RR NS_s) / N) for m = 1..RR-1,
+// k < NS_s, at offset_s + (m-1) NS_s + k.  In total N - R0 entries.
+
+// LDS elements of the exchange buffer of one line.
+template <int N>
+constexpr int fft_lds_elems() {
+  return Shape<N>::PAD ? N + N / Shape<N>::PAD : N;
+}
+
+// Line storage in LDS.  Element e of this thread's line lives at
+// lds[base + e*es] for plain use, and at lds[base + (e + e/PAD)*es] for the
+// FFT exchanges.
+template <typename T>
+struct LineLDS {
+  cx<T>* lds;
+  int base;
+  int es;
+  __device__ __forceinline__ cx<T>& operator[](int e) const { return lds[base + e * es]; }
+  template <int PAD>
+  __device__ __forceinline__ cx<T>& padded(int e) const {
+    if constexpr (PAD == 0) {
+      return lds[base + e * es];
+    } else {
+      return lds[base + (e + e / PAD) * es];
+    }
+  }
+};
+
+template <typename T, int SIGN>
+__device__ __forceinline__ cx<T> twiddle_mul(cx<T> a, cx<T> w) {
+  return SIGN < 0 ? cmul(a, w) : cmulc(a, w);
+}
+
+// One rolled stage of radix RR with stride ns = R0 << sh (sh = log2(RR) (s-1));
+// tws points at this stage's twiddle table in LDS.
+template <typename T, int N, int SIGN, bool LAST>
+__device__ __forceinline__ void rolled_stage(cx<T> (&v)[Shape<N>::P], const LineLDS<T>& L, int t,
+                                             const cx<T>* __restrict__ tws, int sh) {
+  constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, TPL = N / P, B = P / RR;
+  constexpr int PAD = Shape<N>::PAD;
+  const int ns = R0 << sh;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = t + TPL * b;
+    const int q = (j >> sh) / R0;
+    const int k = j - q * ns;
+    cx<T> a[RR];
+#pragma unroll
+    for (int m = 0; m < RR; ++m) a[m] = v[b + m * B];
+#pragma unroll
+    for (int m = 1; m < RR; ++m) a[m] = twiddle_mul<T, SIGN>(a[m], tws[(m - 1) * ns + k]);
+    DFT<RR, SIGN, T>::run(a);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int m = 0; m < RR; ++m) v[b + m * B] = a[m];
+    } else {
+      const int o = q * RR * ns + k;
+#pragma unroll
+      for (int m = 0; m < RR; ++m) L.template padded<PAD>(o + m * ns) = a[m];
+    }
+  }
+}
+
+// In-place transform of the line held in v.  Every thread of the block must
+// call it (it contains block barriers); tw (the stage tables) must be visible
+// in LDS.
+template <typename T, int N, int SIGN>
+__device__ __forceinline__ void fft(cx<T> (&v)[Shape<N>::P], const LineLDS<T>& L, int t,
+                                    const cx<T>* __restrict__ tw) {
+  constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, K = Shape<N>::K;
+  constexpr int TPL = N / P, PAD = Shape<N>::PAD;
+  constexpr int LR = RR == 4 ? 2 : (RR == 8 ? 3 : 4);   // log2(RR)
+  static_assert(P % R0 == 0 && P % RR == 0, "bad shape");
+  {  // stage 0: radix R0, stride 1, no twiddles
+    constexpr int B = P / R0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + TPL * b;
+      cx<T> a[R0];
+#pragma unroll
+      for (int m = 0; m < R0; ++m) a[m] = v[b + m * B];
+      DFT<R0, SIGN, T>::run(a);
+#pragma unroll
+      for (int m = 0; m < R0; ++m) L.template padded<PAD>(j * R0 + m) = a[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = L.template padded<PAD>(t + TPL * s);
+    __syncthreads();
+  }
+  int off = 0;
+#pragma unroll 1
+  for (int sh = 0; sh < LR * (K - 1); sh += LR) {
+    rolled_stage<T, N, SIGN, false>(v, L, t, tw + off, sh);
+    off += (RR - 1) * (R0 << sh);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = L.template padded<PAD>(t + TPL * s);
+    __syncthreads();
+  }
+  rolled_stage<T, N, SIGN, true>(v, L, t, tw + off, LR * (K - 1));
+}
+
+// Copy the stage twiddle tables (N - R0 entries) from global memory to LDS
+// (all threads of the block cooperate; a barrier must follow before use).
+template <typename T, int N>
+__device__ __forceinline__ void stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ src) {
+  for (int u = threadIdx.x; u < N - Shape<N>::R0; u += blockDim.x) dst[u] = src[u];
+}
+
+}  // namespace sofft

@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "internal.hpp"
+#include "line_fft.hpp"
 
 namespace sofft {
 
@@ -128,8 +129,8 @@ sofft_status build_axis(Axis& a, int64_t n, double L, double R0, double theta, i
   a.m = cnt;
   a.j0 = 0;
   if (cnt > 0) {
-    if (cnt >= n - 1) {
-      set_error("the scaled region covers the whole axis; increase R0");
+    if (cnt > n / 2) {
+      set_error("the scaled region covers more than half of the axis; increase R0");
       return SOFFT_EUNSUPPORTED;
     }
     int64_t starts = 0;
@@ -154,12 +155,22 @@ static std::vector<cx<T>> to_cx(const std::vector<zc>& v) {
 }
 
 sofft_status upload_static(Axis& a) {
-  // Twiddles exp(-2 pi i u/n), evaluated in long double and rounded.
-  std::vector<zc> tw(a.n);
+  // Stage twiddle tables of the line FFT (layout in line_fft.hpp), evaluated
+  // in long double and rounded.
+  const ShapeInfo sh = shape_info(a.n);
+  std::vector<zc> tw(a.n, 0.0);
   const long double pil = 3.141592653589793238462643383279502884L;
-  for (int64_t u = 0; u < a.n; ++u) {
-    const long double ang = 2.0L * pil * (long double)u / (long double)a.n;
-    tw[u] = zc(double(cosl(ang)), double(-sinl(ang)));
+  int64_t off = 0, ns = sh.R0;
+  for (int s = 1; s <= sh.K; ++s) {
+    const int64_t stride = a.n / (sh.RR * ns);
+    for (int m = 1; m < sh.RR; ++m)
+      for (int64_t k = 0; k < ns; ++k) {
+        const int64_t u = (m * k * stride) % a.n;
+        const long double ang = 2.0L * pil * (long double)u / (long double)a.n;
+        tw[off + (m - 1) * ns + k] = zc(double(cosl(ang)), double(-sinl(ang)));
+      }
+    off += (sh.RR - 1) * ns;
+    ns *= sh.RR;
   }
   auto t64 = to_cx<double>(tw);
   auto t32 = to_cx<float>(tw);
@@ -310,8 +321,14 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
   }
   sofft_plan* pl = new sofft_plan();
   pl->prob = p;
+  // The 2D passes solve each line's ECS strip in one wavefront, four nodes per
+  // lane: at most 256 strip nodes per axis.
   for (int d = 0; d < p.ndim; ++d) {
     sofft_status st = build_axis(pl->ax[d], p.n[d], p.L[d], p.R0[d], p.theta, p.contour);
+    if (st == SOFFT_OK && p.ndim == 2 && pl->ax[d].m > 256) {
+      set_error("ECS strip of " + std::to_string(pl->ax[d].m) + " nodes exceeds 256 per axis in 2D; increase R0");
+      st = SOFFT_EUNSUPPORTED;
+    }
     if (st == SOFFT_OK) st = upload_static(pl->ax[d]);
     if (st != SOFFT_OK) {
       for (int e = 0; e < 2; ++e) free_axis(pl->ax[e]);
@@ -371,6 +388,102 @@ sofft_status sofft_norm2(sofft_plan* plan, const void* psi, double* norm2_host, 
     return SOFFT_EINVAL;
   }
   return launch_norm2(*plan, psi, norm2_host, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- timing aid
+namespace sofft {
+
+static hipEvent_t take_event(Timing& T) {
+  if (!T.pool.empty()) {
+    hipEvent_t e = T.pool.back();
+    T.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+sofft_status Timing::begin(int kind, hipStream_t s) {
+  if (!on) return SOFFT_OK;
+  if (recs.size() >= 4096) {
+    sofft_status st = drain();
+    if (st != SOFFT_OK) return st;
+  }
+  Rec r{kind, take_event(*this), take_event(*this)};
+  if (!r.a || !r.b) {
+    set_error("hipEventCreate failed");
+    return SOFFT_EHIP;
+  }
+  SOFFT_HIP_TRY(hipEventRecord(r.a, s));
+  recs.push_back(r);
+  return SOFFT_OK;
+}
+
+sofft_status Timing::end(hipStream_t s) {
+  if (!on || recs.empty()) return SOFFT_OK;
+  SOFFT_HIP_TRY(hipEventRecord(recs.back().b, s));
+  return SOFFT_OK;
+}
+
+sofft_status Timing::drain() {
+  for (auto& r : recs) {
+    SOFFT_HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    SOFFT_HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    total_ms[r.kind] += ms;
+    count[r.kind] += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+  return SOFFT_OK;
+}
+
+void Timing::clear() {
+  for (auto& r : recs) {
+    (void)hipEventSynchronize(r.b);
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+  for (int k = 0; k < SOFFT_KERNEL_COUNT_; ++k) {
+    total_ms[k] = 0;
+    count[k] = 0;
+  }
+}
+
+Timing::~Timing() {
+  clear();
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+}  // namespace sofft
+
+extern "C" {
+
+sofft_status sofft_timing_enable(sofft_plan* plan, int32_t enable) {
+  if (!plan) {
+    set_error("null plan");
+    return SOFFT_EINVAL;
+  }
+  plan->timing.clear();
+  plan->timing.on = enable != 0;
+  return SOFFT_OK;
+}
+
+sofft_status sofft_timing_read(sofft_plan* plan, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!plan || !total_ms || !launches || kernel < 0 || kernel >= SOFFT_KERNEL_COUNT_) {
+    set_error("bad argument to sofft_timing_read");
+    return SOFFT_EINVAL;
+  }
+  sofft_status st = plan->timing.drain();
+  if (st != SOFFT_OK) return st;
+  *total_ms = plan->timing.total_ms[kernel];
+  *launches = plan->timing.count[kernel];
+  return SOFFT_OK;
 }
 
 }  // extern "C"

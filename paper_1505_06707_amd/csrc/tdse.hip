@@ -10,7 +10,7 @@
 // 1D: one workgroup keeps the whole line in registers/LDS for all steps.
 #include <algorithm>
 
-#include "fft_line.hpp"
+#include "line_fft.hpp"
 #include "internal.hpp"
 
 namespace sofft {
@@ -30,38 +30,70 @@ struct PassArgs {
   const cx<double>* zx;   // z(x_j)
   const cx<double>* zy;   // z(y_j) (2D) or null
   int j0, m, levels;      // ECS strip of the pass axis
+  int j0y, my;            // ECS strip of the y axis (row pass of a 2D grid)
   const cx<T>* alpha;
   const cx<T>* gamma;
   const cx<T>* binv;
   int lds_line;           // LDS elements reserved per line
 };
 
+// ---------------------------------------------------------------- potential phase
+// exp(-i a) exp(b) for real a, b.  Small arguments (the usual case: U dt/2 of
+// a few hundredths) use Taylor polynomials, which reach the FP64 rounding level
+// for |a|, |b| < 0.3; larger ones go to the math library out of line.
+__device__ __noinline__ cx<double> expi_libm(double a, double b) {
+  double sn, c;
+  sincos(a, &sn, &c);
+  const double e = exp(b);
+  return {e * c, -e * sn};
+}
+
+__device__ __forceinline__ cx<double> expi(double a, double b) {
+  if (!(fabs(a) < 0.3 && fabs(b) < 0.3)) return expi_libm(a, b);
+  const double a2 = a * a;
+  const double sn = a * (1.0 - a2 * (1.0 / 6) * (1.0 - a2 * (1.0 / 20) * (1.0 - a2 * (1.0 / 42) *
+                    (1.0 - a2 * (1.0 / 72) * (1.0 - a2 * (1.0 / 110) * (1.0 - a2 * (1.0 / 156) *
+                    (1.0 - a2 * (1.0 / 210))))))));
+  const double c = 1.0 - a2 * 0.5 * (1.0 - a2 * (1.0 / 12) * (1.0 - a2 * (1.0 / 30) * (1.0 - a2 * (1.0 / 56) *
+                   (1.0 - a2 * (1.0 / 90) * (1.0 - a2 * (1.0 / 132) * (1.0 - a2 * (1.0 / 182)))))));
+  double e = 1.0;
+  if (b != 0.0) {
+    e = 1.0 + b * (1.0 / 15);
+#pragma unroll
+    for (int k = 14; k >= 1; --k) e = 1.0 + b * (1.0 / k) * e;
+  }
+  return {e * c, -e * sn};
+}
+
 // exp(-i U dt/2) with U = -charge/sqrt(s) + f x, s = sum z^2 + a2 (principal
-// branch), evaluated in FP64.
+// branch), in FP64.
 __device__ __forceinline__ cx<double> potential_phase(cx<double> s, double charge, double fx, double ht) {
   double ure = fx, uim = 0.0;
   if (charge != 0.0) {
     if (s.im == 0.0 && s.re > 0.0) {
       ure -= charge / sqrt(s.re);
     } else {
-      const double r = hypot(s.re, s.im);
+      // sqrt(s) = wr + i wi; -charge/sqrt(s) = -charge (wr - i wi)/|s|
+      const double r = sqrt(fma(s.re, s.re, s.im * s.im));
       double wr, wi;
       if (s.re >= 0.0) {
         wr = sqrt(0.5 * (r + s.re));
-        wi = s.im / (2.0 * wr);
+        wi = 0.5 * s.im / wr;
       } else {
         wi = copysign(sqrt(0.5 * (r - s.re)), s.im);
-        wr = s.im / (2.0 * wi);
+        wr = 0.5 * s.im / wi;
       }
-      // -charge / w = -charge conj(w) / |w|^2, |w|^2 = r
-      ure -= charge * wr / r;
-      uim += charge * wi / r;
+      const double q = charge / r;
+      ure -= q * wr;
+      uim += q * wi;
     }
   }
-  double sn, cs;
-  sincos(ure * ht, &sn, &cs);
-  const double mag = uim == 0.0 ? 1.0 : exp(uim * ht);
-  return {mag * cs, -mag * sn};
+  return expi(ure * ht, uim * ht);
+}
+
+__device__ __forceinline__ int strip_pos_rt(int e, int j0, int n) {
+  int p = e - j0;
+  return p < 0 ? p + n : p;
 }
 
 template <typename T>
@@ -69,30 +101,59 @@ __device__ __forceinline__ cx<T> to(cx<double> v) {
   return {T(v.re), T(v.im)};
 }
 
-// Crank-Nicolson on the ECS strip of this line: y = 2 B^-1 v - v by parallel
-// cyclic reduction with the coefficients prepared on the host.  The strip is
-// staged in the line's LDS storage (two buffers of m elements).
-template <typename T, int N, int P>
-__device__ __forceinline__ void cn_strip(cx<T> (&v)[P], const LineLDS<T>& L, int t, const PassArgs<T>& a) {
-  constexpr int TPL = N / P;
+// v * ph with the product formed in FP64 (phases are FP64; rounding them to
+// FP32 first would repeat the same rounding error every step).
+template <typename T>
+__device__ __forceinline__ cx<T> mul_phase(cx<T> v, cx<double> ph) {
+  const cx<double> r = cmul(cx<double>{double(v.re), double(v.im)}, ph);
+  return {T(r.re), T(r.im)};
+}
+
+// Position of element e on the ECS strip of its axis (>= m when outside).
+template <int N>
+__device__ __forceinline__ int strip_pos(int e, int j0) {
+  int p = e - j0;
+  return p < 0 ? p + N : p;
+}
+
+// Crank-Nicolson on the ECS strip of a line held by the whole block (1D):
+// y = 2 B^-1 v - v by parallel cyclic reduction, staged in the line's LDS
+// storage (buffers [0, m) and [m, 2m)).  As in pcr_wave, neighbours are read at
+// clamped indices (the host zeroes the coefficients that reach past the strip)
+// and the next level's coefficients are fetched during the current level.
+template <typename T, int N>
+__device__ __forceinline__ void cn_strip(cx<T> (&v)[Shape<N>::P], const LineLDS<T>& L, int t,
+                                         const PassArgs<T>& a) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
+  constexpr int MAXPOS = P / 2;   // strip positions per thread: the host keeps m <= N/2
   const int m = a.m;
 #pragma unroll
   for (int s = 0; s < P; ++s) {
-    int p = t + TPL * s - a.j0;
-    if (p < 0) p += N;
+    const int p = strip_pos<N>(t + TPL * s, a.j0);
     if (p < m) L[p] = v[s];
+  }
+  cx<T> al[MAXPOS], ga[MAXPOS];
+  if (a.levels > 0) {
+#pragma unroll
+    for (int i = 0; i < MAXPOS; ++i) {
+      const int p = min(t + TPL * i, m - 1);
+      al[i] = a.alpha[p];
+      ga[i] = a.gamma[p];
+    }
   }
   __syncthreads();
   int src = 0, dst = m;
   for (int l = 0; l < a.levels; ++l) {
     const int st = 1 << l;
-    const cx<T>* al = a.alpha + size_t(l) * m;
-    const cx<T>* ga = a.gamma + size_t(l) * m;
-    for (int p = t; p < m; p += TPL) {
-      cx<T> d = L[src + p];
-      if (p >= st) d = d - cmul(al[p], L[src + p - st]);
-      if (p + st < m) d = d - cmul(ga[p], L[src + p + st]);
-      L[dst + p] = d;
+    const cx<T>* aln = a.alpha + size_t(l + 1 < a.levels ? l + 1 : l) * m;
+    const cx<T>* gan = a.gamma + size_t(l + 1 < a.levels ? l + 1 : l) * m;
+#pragma unroll
+    for (int i = 0; i < MAXPOS; ++i) {
+      const int p0 = t + TPL * i, p = min(p0, m - 1);
+      const cx<T> d = L[src + p] - cmul(al[i], L[src + max(p - st, 0)]) - cmul(ga[i], L[src + min(p + st, m - 1)]);
+      al[i] = aln[p];
+      ga[i] = gan[p];
+      if (p0 < m) L[dst + p] = d;
     }
     __syncthreads();
     const int tmp = src;
@@ -101,43 +162,202 @@ __device__ __forceinline__ void cn_strip(cx<T> (&v)[P], const LineLDS<T>& L, int
   }
 #pragma unroll
   for (int s = 0; s < P; ++s) {
-    int p = t + TPL * s - a.j0;
-    if (p < 0) p += N;
+    const int p = strip_pos<N>(t + TPL * s, a.j0);
     if (p < m) v[s] = T(2) * cmul(a.binv[p], L[src + p]) - v[s];
   }
   __syncthreads();
 }
 
+// U/2 . C . U/2 along a line whose cross coordinate is fixed (1D, or a 2D row
+// outside the y-strip): outside the strip the two half-steps are one multiply
+// by the squared phase; on the strip the phase is parked in LDS (from 2m)
+// across the CN.  With both_halves false only the first half-step and C apply.
+template <typename T, int N, typename PhaseFn>
+__device__ __forceinline__ void pot_cn_pot(cx<T> (&v)[Shape<N>::P], const LineLDS<T>& L, int t,
+                                           const PassArgs<T>& a, bool both_halves, PhaseFn phase) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
+  const int m = a.m;
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int e = t + TPL * s;
+    const cx<double> ph = phase(e);
+    const int p = strip_pos<N>(e, a.j0);
+    if (p < m) {
+      v[s] = mul_phase(v[s], ph);
+      if (both_halves) L[2 * m + p] = to<T>(ph);
+    } else {
+      v[s] = mul_phase(v[s], both_halves ? cmul(ph, ph) : ph);
+    }
+  }
+  if (m > 0) {
+    cn_strip<T, N>(v, L, t, a);
+    if (both_halves) {
+#pragma unroll
+      for (int s = 0; s < P; ++s) {
+        const int p = strip_pos<N>(t + TPL * s, a.j0);
+        if (p < m) v[s] = cmul(v[s], L[2 * m + p]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Blocks of the 2D passes have 256 threads (one 1024-point line, or several
+// shorter ones), so that several independent blocks share a CU and one
+// block's barriers overlap another's work.  P = 4 shapes keep <= 128 VGPRs
+// (4 waves per SIMD); P = 12 shapes (radix 3) need more and run 2.
+#ifndef SOFFT_ROW_THREADS
+#define SOFFT_ROW_THREADS 1024
+#endif
+#ifndef SOFFT_COL_THREADS
+#define SOFFT_COL_THREADS 1024
+#endif
+constexpr int kRowThreads = SOFFT_ROW_THREADS;
+constexpr int kColThreads = SOFFT_COL_THREADS;
+template <int N>
+constexpr int min_waves_per_simd() {
+  return Shape<N>::P == 4 ? 4 : 2;
+}
+template <int N, int THREADS>
+constexpr int block_threads() {   // at least one whole line
+  return N / Shape<N>::P > THREADS ? N / Shape<N>::P : THREADS;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Crank-Nicolson solve B u = v on one line's strip by one wavefront: parallel
+// cyclic reduction, lane owning positions p = lane + 64 i (i < 4: the host
+// keeps the 2D strips at m <= 256).  The host zeroes alpha where p - 2^l < 0
+// and gamma where p + 2^l >= m, so neighbours are read at clamped indices
+// without branches; the next level's coefficients are fetched while the
+// current level is reduced.  Levels ping-pong between [0, m) and [m, 2m); on
+// entry [0, m) holds v, on exit u is in the buffer cn_result(m, levels).
+constexpr int kPcrPos = 4;
+__host__ __device__ __forceinline__ int cn_result(int m, int levels) { return (levels & 1) ? 0 : m; }
+
 template <typename T, int N>
-__global__ void __launch_bounds__(256) k_row_pass(PassArgs<T> a) {
-  constexpr int P = FFTShape<N>::P, TPL = N / P, LPB = 256 / TPL;
+__device__ __forceinline__ void pcr_wave(const LineLDS<T>& Lw, int lane, const PassArgs<T>& a) {
+  constexpr int W = N / 128 > 0 ? (N / 128 < kPcrPos ? N / 128 : kPcrPos) : 1;
+  const int m = a.m, levels = a.levels;
+  int src = 0, dst = m;
+  cx<T> al[W], ga[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const int p = min(lane + 64 * i, m - 1);
+    if (levels > 0) {
+      al[i] = a.alpha[p];
+      ga[i] = a.gamma[p];
+    }
+  }
+  for (int l = 0; l < levels; ++l) {
+    const int st = 1 << l;
+    const cx<T>* aln = a.alpha + size_t(l + 1 < levels ? l + 1 : l) * m;
+    const cx<T>* gan = a.gamma + size_t(l + 1 < levels ? l + 1 : l) * m;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      const int p0 = lane + 64 * i, p = min(p0, m - 1);
+      const cx<T> d = Lw[src + p] - cmul(al[i], Lw[src + max(p - st, 0)]) - cmul(ga[i], Lw[src + min(p + st, m - 1)]);
+      al[i] = aln[p];
+      ga[i] = gan[p];
+      if (p0 < m) Lw[dst + p] = d;
+    }
+    wave_sync();
+    const int tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const int p0 = lane + 64 * i, p = min(p0, m - 1);
+    const cx<T> u = cmul(a.binv[p], Lw[src + p]);
+    if (p0 < m) Lw[dst + p] = u;
+  }
+}
+
+// All lines of the block: wavefront w solves the strips of lines w, w +
+// nwaves, ...; line_of(ln) gives the LDS view of line ln.  Block barriers
+// before and after.
+template <typename T, int N, typename LineOf>
+__device__ __forceinline__ void cn_block(int lpb, const PassArgs<T>& a, LineOf line_of) {
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int ln = w; ln < lpb; ln += nw) pcr_wave<T, N>(line_of(ln), lane, a);
+  __syncthreads();
+}
+
+// Block LDS layout of the 2D passes: [line 0][line 1]...; a block holds
+// blockDim.x / TPL lines of a.lds_line elements.  FFT twiddles and CN
+// coefficients are read from global memory (they stay in the vector L1).
+template <typename T, int N>
+__global__ void __launch_bounds__((block_threads<N, kRowThreads>()), min_waves_per_simd<N>()) k_row_pass(PassArgs<T> a) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* lines = reinterpret_cast<cx<T>*>(smem);
+  const int lpb = blockDim.x / TPL;
   const int l = threadIdx.x / TPL, t = threadIdx.x - l * TPL;
-  const int row = blockIdx.x * LPB + l;
+  const int row = blockIdx.x * lpb + l;
   const bool live = row < a.ny;
   const int crow = live ? row : 0;
-  const LineLDS<T> L{lds, l * a.lds_line, 1};
+  const LineLDS<T> L{lines, l * a.lds_line, 1};
   cx<T>* line = a.psi + size_t(crow) * N;
-  cx<T> v[P];
+  const bool cn = a.do_pot && a.m > 0;
+  cx<T> v[P], kin[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = live ? line[t + TPL * s] : cx<T>{T(0), T(0)};
-  fft_line<T, N, -1>(v, L, t, a.tw);
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = cmul(v[s], a.kin[t + TPL * s]);
-  fft_line<T, N, +1>(v, L, t, a.tw);
+  for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
+  // inputs of the potential, fetched before the transforms
+  cx<double> zxs[P];
+  double xs[P];
+  double f = 0.0;
+  cx<double> zy{0.0, 0.0};
   if (a.do_pot) {
-    const double f = a.f_mid ? a.f_mid[a.step] : 0.0;
-    const cx<double> zy = a.zy ? a.zy[crow] : cx<double>{0.0, 0.0};
-    const cx<double> zy2a = cmul(zy, zy) + cx<double>{a.a2, 0.0};
 #pragma unroll
     for (int s = 0; s < P; ++s) {
-      const int e = t + TPL * s;
-      const cx<double> zx = a.zx[e];
-      const cx<double> ph = potential_phase(cmul(zx, zx) + zy2a, a.charge, f * a.x[e], a.ht);
-      v[s] = cmul(v[s], to<T>(ph));
+      zxs[s] = a.zx[t + TPL * s];
+      xs[s] = a.x[t + TPL * s];
     }
-    if (a.m > 0) cn_strip<T, N, P>(v, L, t, a);
+    f = a.f_mid ? a.f_mid[a.step] : 0.0;
+    if (a.zy) zy = a.zy[crow];
+  }
+  fft<T, N, -1>(v, L, t, a.tw);
+#pragma unroll
+  for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
+  fft<T, N, +1>(v, L, t, a.tw);
+  if (a.do_pot) {
+    // Rows outside the y-strip get both potential half-steps here (C_y is the
+    // identity on them); rows on it get the first, the column pass the second.
+    // On the x-strip the phase waits in LDS (from 2m) across the CN.
+    const cx<double> zy2a = cmul(zy, zy) + cx<double>{a.a2, 0.0};
+    const bool both = strip_pos_rt(crow, a.j0y, a.ny) >= a.my;
+    const int m = a.m;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const cx<double> ph = potential_phase(cmul(zxs[s], zxs[s]) + zy2a, a.charge, f * xs[s], a.ht);
+      const int p = strip_pos<N>(t + TPL * s, a.j0);
+      if (p < m) {
+        v[s] = mul_phase(v[s], ph);
+        L[p] = v[s];
+        if (both) L[2 * m + p] = to<T>(ph);
+      } else {
+        v[s] = mul_phase(v[s], both ? cmul(ph, ph) : ph);
+      }
+    }
+    if (cn) {
+      cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<T>{lines, ln * a.lds_line, 1}; });
+#pragma unroll
+      for (int s = 0; s < P; ++s) {
+        const int p = strip_pos<N>(t + TPL * s, a.j0);
+        if (p < m) {
+          v[s] = T(2) * L[cn_result(m, a.levels) + p] - v[s];
+          if (both) v[s] = cmul(v[s], L[2 * m + p]);
+        }
+      }
+    }
   }
   if (live) {
 #pragma unroll
@@ -145,38 +365,62 @@ __global__ void __launch_bounds__(256) k_row_pass(PassArgs<T> a) {
   }
 }
 
+// Column blocks are assigned so that the blocks one XCD runs hold adjacent
+// columns (workgroups go round-robin over the 8 XCDs): neighbouring columns
+// share 128-byte lines, which then meet in the same L2.
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+  if (nblk % 8 != 0) return b;
+  return (b % 8) * (nblk / 8) + b / 8;
+}
+
 template <typename T, int N>
-__global__ void __launch_bounds__(256) k_col_pass(PassArgs<T> a) {
-  constexpr int P = FFTShape<N>::P, TPL = N / P, C = 256 / TPL;
+__global__ void __launch_bounds__((block_threads<N, kColThreads>()), min_waves_per_simd<N>()) k_col_pass(PassArgs<T> a) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
-  const int c = threadIdx.x % C, t = threadIdx.x / C;
-  const int col = blockIdx.x * C + c;
+  cx<T>* lines = reinterpret_cast<cx<T>*>(smem);
+  const int lpb = blockDim.x / TPL;
+  const int c = threadIdx.x % lpb, t = threadIdx.x / lpb;
+  const int col = xcd_block(blockIdx.x, gridDim.x) * lpb + c;
   const bool live = col < a.nx;
   const int ccol = live ? col : 0;
-  const LineLDS<T> L{lds, c, C};
+  const LineLDS<T> L{lines, c, lpb};
   cx<T>* base = a.psi + ccol;
   const size_t ld = size_t(a.nx);
-  cx<T> v[P];
+  const bool cn = a.do_pot && a.m > 0;
+  cx<T> v[P], kin[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = live ? base[size_t(t + TPL * s) * ld] : cx<T>{T(0), T(0)};
-  if (a.do_pot) {
-    if (a.m > 0) cn_strip<T, N, P>(v, L, t, a);
+#pragma unroll
+  for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
+  if (cn) {
+    // C_y and the second potential half-step, on the y-strip only.
     const double f = a.f_mid ? a.f_mid[a.step] : 0.0;
     const cx<double> zx = a.zx[ccol];
-    const cx<double> zx2a = cmul(zx, zx) + cx<double>{a.a2, 0.0};
     const double fx = f * a.x[ccol];
+    const int m = a.m;
 #pragma unroll
     for (int s = 0; s < P; ++s) {
-      const cx<double> zy = a.zy[t + TPL * s];
-      const cx<double> ph = potential_phase(zx2a + cmul(zy, zy), a.charge, fx, a.ht);
-      v[s] = cmul(v[s], to<T>(ph));
+      const int p = strip_pos<N>(t + TPL * s, a.j0);
+      if (p < m) L[p] = v[s];
     }
-  }
-  fft_line<T, N, -1>(v, L, t, a.tw);
+    cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<T>{lines, ln, lpb}; });
+    const cx<double> zx2a = cmul(zx, zx) + cx<double>{a.a2, 0.0};
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = cmul(v[s], a.kin[t + TPL * s]);
-  fft_line<T, N, +1>(v, L, t, a.tw);
+    for (int s = 0; s < P; ++s) {
+      const int e = t + TPL * s;
+      const int p = strip_pos<N>(e, a.j0);
+      if (p < m) {
+        const cx<double> zy = a.zy[e];
+        v[s] = mul_phase(T(2) * L[cn_result(m, a.levels) + p] - v[s],
+                         potential_phase(zx2a + cmul(zy, zy), a.charge, fx, a.ht));
+      }
+    }
+    __syncthreads();
+  }
+  fft<T, N, -1>(v, L, t, a.tw);
+#pragma unroll
+  for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
+  fft<T, N, +1>(v, L, t, a.tw);
   if (live) {
 #pragma unroll
     for (int s = 0; s < P; ++s) base[size_t(t + TPL * s) * ld] = v[s];
@@ -185,38 +429,37 @@ __global__ void __launch_bounds__(256) k_col_pass(PassArgs<T> a) {
 
 // 1D: the whole propagation in one workgroup; psi stays in registers.
 template <typename T, int N>
-__global__ void __launch_bounds__(N / FFTShape<N>::P) k_tdse1d(PassArgs<T> a, const cx<T>* kin_half,
-                                                                const cx<T>* kin_full, int64_t nsteps) {
-  constexpr int P = FFTShape<N>::P, TPL = N / P;
+__global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const cx<T>* kin_half,
+                                                             const cx<T>* kin_full, int64_t nsteps) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
   const int t = threadIdx.x;
-  const LineLDS<T> L{lds, 0, 1};
-  cx<T> v[P];
+  const LineLDS<T> L{tw + N, 0, 1};
+  cx<T> v[P], kf[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = a.psi[t + TPL * s];
-  fft_line<T, N, -1>(v, L, t, a.tw);
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin_half[t + TPL * s]);
-  fft_line<T, N, +1>(v, L, t, a.tw);
+  for (int s = 0; s < P; ++s) kf[s] = kin_half[t + TPL * s];
+  stage_twiddles<T, N>(tw, a.tw);
+  __syncthreads();
+  fft<T, N, -1>(v, L, t, tw);
+#pragma unroll
+  for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kf[s]);
+  fft<T, N, +1>(v, L, t, tw);
   for (int64_t n = 0; n < nsteps; ++n) {
     const double f = a.f_mid ? a.f_mid[n] : 0.0;
-    cx<T> ph[P];
-#pragma unroll
-    for (int s = 0; s < P; ++s) {
-      const int e = t + TPL * s;
+    pot_cn_pot<T, N>(v, L, t, a, true, [&](int e) {
       const cx<double> z = a.zx[e];
-      ph[s] = to<T>(potential_phase(cmul(z, z) + cx<double>{a.a2, 0.0}, a.charge, f * a.x[e], a.ht));
-      v[s] = cmul(v[s], ph[s]);
-    }
-    if (a.m > 0) cn_strip<T, N, P>(v, L, t, a);
+      return potential_phase(cmul(z, z) + cx<double>{a.a2, 0.0}, a.charge, f * a.x[e], a.ht);
+    });
+    const cx<T>* kin = n + 1 == nsteps ? kin_half : kin_full;
 #pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = cmul(v[s], ph[s]);
-    const cx<T>* kin = (n + 1 == nsteps) ? kin_half : kin_full;
-    fft_line<T, N, -1>(v, L, t, a.tw);
+    for (int s = 0; s < P; ++s) kf[s] = kin[t + TPL * s];
+    fft<T, N, -1>(v, L, t, tw);
 #pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[t + TPL * s]);
-    fft_line<T, N, +1>(v, L, t, a.tw);
+    for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kf[s]);
+    fft<T, N, +1>(v, L, t, tw);
   }
 #pragma unroll
   for (int s = 0; s < P; ++s) a.psi[t + TPL * s] = v[s];
@@ -246,6 +489,20 @@ static const cx<T>* tab(const DevBuf& b64, const DevBuf& b32) {
   return static_cast<const cx<T>*>(std::is_same<T, double>::value ? b64.p : b32.p);
 }
 
+static int64_t lds_elems_for(int64_t n) {
+  switch (n) {
+#define SOFFT_LDS_CASE(N) \
+  case N:                 \
+    return fft_lds_elems<N>();
+    SOFFT_LDS_CASE(16) SOFFT_LDS_CASE(32) SOFFT_LDS_CASE(48) SOFFT_LDS_CASE(64) SOFFT_LDS_CASE(96)
+    SOFFT_LDS_CASE(128) SOFFT_LDS_CASE(192) SOFFT_LDS_CASE(256) SOFFT_LDS_CASE(384) SOFFT_LDS_CASE(512)
+    SOFFT_LDS_CASE(768) SOFFT_LDS_CASE(1024) SOFFT_LDS_CASE(2048) SOFFT_LDS_CASE(4096)
+#undef SOFFT_LDS_CASE
+    default:
+      return 2 * n;
+  }
+}
+
 template <typename T>
 static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   Axis& A = p.ax[axis];
@@ -266,15 +523,25 @@ static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   a.alpha = tab<T>(A.alpha64, A.alpha32);
   a.gamma = tab<T>(A.gamma64, A.gamma32);
   a.binv = tab<T>(A.binv64, A.binv32);
-  a.lds_line = int(std::max<int64_t>(A.n, 2 * A.m));
+  a.lds_line = int(std::max<int64_t>(lds_elems_for(A.n), 3 * A.m));
+  // y-strip, used by the row pass to decide which rows take both half-steps
+  a.j0y = p.prob.ndim == 2 ? int(p.ax[1].j0) : 0;
+  a.my = p.prob.ndim == 2 ? int(p.ax[1].m) : 0;
   return a;
 }
 
+// LDS budget per block (MI355X has 160 KiB per CU; leave room for the runtime).
+constexpr size_t kLdsBudget = 150 * 1024;
+
+// Raise a kernel's dynamic LDS limit once (to the whole budget) the first time
+// it needs more than the default 64 KiB.
 template <typename K>
 static sofft_status set_lds(K kernel, size_t bytes) {
-  if (bytes > 65536) {
+  static bool raised = false;   // one flag per kernel instantiation
+  if (bytes > 65536 && !raised) {
     SOFFT_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsBudget)));
+    raised = true;
   }
   return SOFFT_OK;
 }
@@ -296,40 +563,61 @@ static sofft_status set_lds(K kernel, size_t bytes) {
     default: break;                               \
   }
 
-template <typename T, int N>
-static sofft_status row_pass(const PassArgs<T>& a, hipStream_t s) {
-  constexpr int TPL = N / FFTShape<N>::P, LPB = 256 / TPL;
-  const size_t lds = size_t(LPB) * a.lds_line * sizeof(cx<T>);
-  sofft_status st = set_lds(k_row_pass<T, N>, lds);
-  if (st != SOFFT_OK) return st;
-  const int blocks = (a.ny + LPB - 1) / LPB;
-  k_row_pass<T, N><<<blocks, 256, lds, s>>>(a);
-  SOFFT_HIP_TRY(hipGetLastError());
-  return SOFFT_OK;
+// Lines per block of a 2D pass with THREADS threads per block (at least one).
+template <typename T, int N, int THREADS>
+static int lines_per_block(int lds_line, size_t* lds_bytes) {
+  constexpr int TPL = N / Shape<N>::P;
+  const int lpb = TPL >= THREADS ? 1 : THREADS / TPL;
+  *lds_bytes = size_t(lpb) * lds_line * sizeof(cx<T>);
+  return *lds_bytes > kLdsBudget ? 0 : lpb;
 }
 
 template <typename T, int N>
-static sofft_status col_pass(const PassArgs<T>& a, hipStream_t s) {
-  constexpr int TPL = N / FFTShape<N>::P, C = 256 / TPL;
-  const size_t lds = size_t(C) * a.lds_line * sizeof(cx<T>);
+static sofft_status row_pass(const PassArgs<T>& a, hipStream_t s, Timing& tm) {
+  constexpr int TPL = N / Shape<N>::P;
+  size_t lds = 0;
+  const int lpb = lines_per_block<T, N, kRowThreads>(a.lds_line, &lds);
+  if (lpb == 0) {
+    set_error("ECS strip too long for the LDS budget");
+    return SOFFT_EUNSUPPORTED;
+  }
+  sofft_status st = set_lds(k_row_pass<T, N>, lds);
+  if (st != SOFFT_OK) return st;
+  const int blocks = (a.ny + lpb - 1) / lpb;
+  if ((st = tm.begin(SOFFT_KERNEL_ROW, s)) != SOFFT_OK) return st;
+  k_row_pass<T, N><<<blocks, lpb * TPL, lds, s>>>(a);
+  SOFFT_HIP_TRY(hipGetLastError());
+  return tm.end(s);
+}
+
+template <typename T, int N>
+static sofft_status col_pass(const PassArgs<T>& a, hipStream_t s, Timing& tm) {
+  constexpr int TPL = N / Shape<N>::P;
+  size_t lds = 0;
+  const int lpb = lines_per_block<T, N, kColThreads>(a.lds_line, &lds);
+  if (lpb == 0) {
+    set_error("ECS strip too long for the LDS budget");
+    return SOFFT_EUNSUPPORTED;
+  }
   sofft_status st = set_lds(k_col_pass<T, N>, lds);
   if (st != SOFFT_OK) return st;
-  const int blocks = (a.nx + C - 1) / C;
-  k_col_pass<T, N><<<blocks, 256, lds, s>>>(a);
+  const int blocks = (a.nx + lpb - 1) / lpb;
+  if ((st = tm.begin(SOFFT_KERNEL_COL, s)) != SOFFT_OK) return st;
+  k_col_pass<T, N><<<blocks, lpb * TPL, lds, s>>>(a);
   SOFFT_HIP_TRY(hipGetLastError());
-  return SOFFT_OK;
+  return tm.end(s);
 }
 
 template <typename T>
-static sofft_status row_pass_n(int n, const PassArgs<T>& a, hipStream_t s) {
-  SOFFT_LENGTH_SWITCH(n, row_pass, T, a, s)
+static sofft_status row_pass_n(int n, const PassArgs<T>& a, hipStream_t s, Timing& tm) {
+  SOFFT_LENGTH_SWITCH(n, row_pass, T, a, s, tm)
   set_error("unsupported row length");
   return SOFFT_EUNSUPPORTED;
 }
 
 template <typename T>
-static sofft_status col_pass_n(int n, const PassArgs<T>& a, hipStream_t s) {
-  SOFFT_LENGTH_SWITCH(n, col_pass, T, a, s)
+static sofft_status col_pass_n(int n, const PassArgs<T>& a, hipStream_t s, Timing& tm) {
+  SOFFT_LENGTH_SWITCH(n, col_pass, T, a, s, tm)
   set_error("unsupported column length");
   return SOFFT_EUNSUPPORTED;
 }
@@ -349,32 +637,37 @@ static sofft_status propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, 
   // opening K_y/2
   ca.do_pot = 0;
   ca.kin = kyh;
-  if ((st = col_pass_n<T>(ny, ca, s)) != SOFFT_OK) return st;
+  if ((st = col_pass_n<T>(ny, ca, s, p.timing)) != SOFFT_OK) return st;
   ra.do_pot = ca.do_pot = 1;
   for (int64_t n = 0; n < nsteps; ++n) {
     ra.step = ca.step = n;
     ra.kin = n == 0 ? kxh : kxf;
     ca.kin = n + 1 == nsteps ? kyh : kyf;
-    if ((st = row_pass_n<T>(nx, ra, s)) != SOFFT_OK) return st;
-    if ((st = col_pass_n<T>(ny, ca, s)) != SOFFT_OK) return st;
+    if ((st = row_pass_n<T>(nx, ra, s, p.timing)) != SOFFT_OK) return st;
+    if ((st = col_pass_n<T>(ny, ca, s, p.timing)) != SOFFT_OK) return st;
   }
   // closing K_x/2
   ra.do_pot = 0;
   ra.kin = kxh;
-  return row_pass_n<T>(nx, ra, s);
+  return row_pass_n<T>(nx, ra, s, p.timing);
 }
 
 template <typename T, int N>
 static sofft_status tdse1d(Plan& p, const PassArgs<T>& a, int64_t nsteps, hipStream_t s) {
-  constexpr int TPL = N / FFTShape<N>::P;
-  const size_t lds = size_t(a.lds_line) * sizeof(cx<T>);
+  constexpr int TPL = N / Shape<N>::P;
+  const size_t lds = size_t(N + a.lds_line) * sizeof(cx<T>);
+  if (lds > kLdsBudget) {
+    set_error("ECS strip too long for the LDS budget");
+    return SOFFT_EUNSUPPORTED;
+  }
   sofft_status st = set_lds(k_tdse1d<T, N>, lds);
   if (st != SOFFT_OK) return st;
   const Axis& A = p.ax[0];
+  if ((st = p.timing.begin(SOFFT_KERNEL_1D, s)) != SOFFT_OK) return st;
   k_tdse1d<T, N><<<1, TPL, lds, s>>>(a, tab<T>(A.kin_half64, A.kin_half32), tab<T>(A.kin_full64, A.kin_full32),
                                     nsteps);
   SOFFT_HIP_TRY(hipGetLastError());
-  return SOFFT_OK;
+  return p.timing.end(s);
 }
 
 template <typename T>

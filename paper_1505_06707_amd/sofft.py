@@ -54,7 +54,12 @@ _SIGS = {
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_norm2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.c_void_p]),
+    "sofft_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sofft_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64)]),
 }
+
+KERNEL_ROW, KERNEL_COL, KERNEL_1D = 0, 1, 2
 
 
 def exported_symbols():
@@ -168,6 +173,17 @@ class Plan:
         fptr = ctypes.c_void_p(0) if f_mid is None else _dev_ptr(f_mid, torch.float64, nsteps, "f_mid")
         _check(lib().sofft_propagate(self._h, ptr, float(dt), int(nsteps), fptr, _stream(stream)))
         return psi
+
+    def timing(self, enable=True):
+        """Enable (clearing the record) or disable per-launch event timing."""
+        _check(lib().sofft_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_read(self, kernel):
+        """(total milliseconds, launches) of one kernel kind since enabling."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib().sofft_timing_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
 
     def norm2(self, psi, stream=None):
         ptr = _dev_ptr(psi, self.torch_dtype, self.numel, "psi")
