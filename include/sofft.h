@@ -111,11 +111,52 @@ sofft_status sofft_propagate(sofft_plan* plan, void* psi, double dt, int64_t nst
 /* ||psi||^2 = sum |psi_j|^2 accumulated in FP64 (blocking: waits for the stream). */
 sofft_status sofft_norm2(sofft_plan* plan, const void* psi, double* norm2_host, void* stream);
 
+/* Outcome of one energy of sofft_sse_solve. */
+typedef struct {
+  int32_t iterations;    /* COCG iterations (all restarts included) */
+  int32_t status;        /* SOFFT_OK, SOFFT_NOT_CONVERGED or SOFFT_BREAKDOWN */
+  int32_t restarts;      /* restarts from the true residual */
+  int32_t reserved_;
+  double rel_residual;   /* ||f - A x|| / ||f||, recomputed from x (Hermitian 2-norm) */
+} sofft_solve_stats;
+
+/* Solve the stationary equation with exterior complex scaling of Sec. III,
+ *   [K_s + U - E_j] x_j = f   (Eq. linsys: A = F^-1 K F + C + U - E I),
+ * for nE energies at once by preconditioned conjugate gradients for the
+ * complex-symmetric A (COCG: unconjugated u^T v) with the FFT preconditioner
+ * P^-1 = F^-1 (K - E)^-1 F of Eq. PreconFFT, starting from x = 0.  U is the
+ * static potential of the plan plus field * x (field = 0 after a pulse).
+ * Iterations stop when ||r|| / ||f|| <= rtol (Hermitian 2-norm of the
+ * recurrence residual); the residual is then recomputed as f - A x and the
+ * iteration restarts from it while that exceeds rtol.
+ *   f       device, [n_y][n_x] (f_per_energy = 0, shared) or [nE][n_y][n_x]
+ *   E_host  host, nE energies
+ *   x_out   device, [nE][n_y][n_x], written
+ *   stats   host, nE entries (may be NULL)
+ * 2D complex128 plans only.  The plan allocates a workspace of about
+ * 6 nE n_x n_y * 16 bytes on first use (kept until sofft_plan_destroy).
+ * Blocking: returns after the solve.  Returns SOFFT_OK when every energy met
+ * rtol, else SOFFT_NOT_CONVERGED / SOFFT_BREAKDOWN (per energy in stats). */
+sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
+                             int32_t nE, double field, void* x_out, double rtol, int32_t maxit,
+                             sofft_solve_stats* stats, void* stream);
+
+/* One application of the stationary matrix (op 0: w = A v, Eq. linsys) or of
+ * the FFT preconditioner (op 1: w = P^-1 v, Eq. PreconFFT) at energy E, on
+ * device vectors [n_y][n_x].  Asynchronous on the stream. */
+sofft_status sofft_sse_apply(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double field,
+                             void* stream);
+
 /* Kernels whose launches can be timed (see sofft_timing_*). */
 typedef enum {
   SOFFT_KERNEL_ROW = 0,   /* 2D row pass (x lines) of the propagation */
   SOFFT_KERNEL_COL = 1,   /* 2D column pass (y lines) of the propagation */
   SOFFT_KERNEL_1D = 2,    /* 1D whole-propagation kernel */
+  SOFFT_KERNEL_SSE_ROW_MV = 3,    /* stationary solver: p update + row part of A p */
+  SOFFT_KERNEL_SSE_COL_MV = 4,    /* column part of A p and p^T A p */
+  SOFFT_KERNEL_SSE_ROW_UPD = 5,   /* x, r update, ||r||^2, forward row FFT of r */
+  SOFFT_KERNEL_SSE_COL_PREC = 6,  /* column FFT, divide by k^2/2 - E, inverse */
+  SOFFT_KERNEL_SSE_ROW_PREC = 7,  /* inverse row FFT to z and r^T z */
   SOFFT_KERNEL_COUNT_ = 16
 } sofft_kernel;
 

@@ -76,6 +76,7 @@ struct Plan {
   DevBuf partials;   // reduction scratch (norms)
   std::vector<double> host_partials;
   Timing timing;
+  DevBuf sse_ws, sse_E;   // stationary-solver workspace and energies
 };
 
 // Table builders (plan.hip).
@@ -93,5 +94,10 @@ sofft_status launch_propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, 
                                  hipStream_t s);
 sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s);
 bool supported_length(int64_t n);
+
+// Stationary solver (sse.hip).
+sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E_host, int nE, double field,
+                       void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s);
+sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s);
 
 }  // namespace sofft

@@ -176,6 +176,19 @@ sofft_status upload_static(Axis& a) {
   auto t32 = to_cx<float>(tw);
   auto z64 = to_cx<double>(a.z);
   sofft_status st;
+  // Rows of C on the strip, [C_{j,j-1} (m) | C_{j,j} (m) | C_{j,j+1} (m)] at
+  // j = (j0 + p) mod n, for the stationary matrix-vector product.
+  if (a.m > 0) {
+    std::vector<zc> cs(3 * a.m);
+    for (int64_t p = 0; p < a.m; ++p) {
+      const int64_t j = (a.j0 + p) % a.n;
+      cs[p] = a.cdn[j];
+      cs[a.m + p] = a.cdg[j];
+      cs[2 * a.m + p] = a.cup[j];
+    }
+    auto c64 = to_cx<double>(cs);
+    if ((st = dev_upload(a.cstrip64, c64.data(), c64.size() * sizeof(c64[0]))) != SOFFT_OK) return st;
+  }
   if ((st = dev_upload(a.tw64, t64.data(), t64.size() * sizeof(t64[0]))) != SOFFT_OK) return st;
   if ((st = dev_upload(a.tw32, t32.data(), t32.size() * sizeof(t32[0]))) != SOFFT_OK) return st;
   if ((st = dev_upload(a.x_dev, a.x.data(), a.x.size() * sizeof(double))) != SOFFT_OK) return st;
@@ -344,6 +357,8 @@ sofft_status sofft_plan_destroy(sofft_plan* plan) {
   if (!plan) return SOFFT_OK;
   for (int d = 0; d < 2; ++d) free_axis(plan->ax[d]);
   dev_free(plan->partials);
+  dev_free(plan->sse_ws);
+  dev_free(plan->sse_E);
   delete plan;
   return SOFFT_OK;
 }
@@ -380,6 +395,31 @@ sofft_status sofft_propagate(sofft_plan* plan, void* psi, double dt, int64_t nst
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return plan->prob.ndim == 1 ? launch_propagate_1d(*plan, psi, dt, nsteps, f_mid, s)
                               : launch_propagate_2d(*plan, psi, dt, nsteps, f_mid, s);
+}
+
+sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
+                             int32_t nE, double field, void* x_out, double rtol, int32_t maxit,
+                             sofft_solve_stats* stats, void* stream) {
+  if (!plan || !f || !E_host || nE <= 0 || !x_out || !(rtol > 0) || maxit <= 0 || !std::isfinite(field)) {
+    set_error("bad argument to sofft_sse_solve");
+    return SOFFT_EINVAL;
+  }
+  for (int e = 0; e < nE; ++e)
+    if (!std::isfinite(E_host[e])) {
+      set_error("energies must be finite");
+      return SOFFT_EINVAL;
+    }
+  return sse_solve(*plan, f, f_per_energy, E_host, nE, field, x_out, rtol, maxit, stats,
+                   reinterpret_cast<hipStream_t>(stream));
+}
+
+sofft_status sofft_sse_apply(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double field,
+                             void* stream) {
+  if (!plan || !v || !w || (op != 0 && op != 1) || !std::isfinite(E) || !std::isfinite(field)) {
+    set_error("bad argument to sofft_sse_apply");
+    return SOFFT_EINVAL;
+  }
+  return sse_apply(*plan, op, v, w, E, field, reinterpret_cast<hipStream_t>(stream));
 }
 
 sofft_status sofft_norm2(sofft_plan* plan, const void* psi, double* norm2_host, void* stream) {

@@ -1,0 +1,767 @@
+// Stationary equation with ECS and its FFT-preconditioned conjugate-gradient
+// solve (Sec. III), batched over energies, on CDNA4.
+//
+// A v = F^-1 K F v + C v + (U - E) v (Eq. linsys).  In 2D the kinetic term is
+// additive, T_x v + T_y v, so A v takes two passes: the row pass writes
+// w1 = T_x v + C_x v + (U - E) v, the column pass adds T_y v + C_y v.  The
+// preconditioner P^-1 r = F^-1 (K - E)^-1 F r (Eq. PreconFFT) is a full 2D
+// transform: forward along rows (fused into the residual update), forward,
+// divide and inverse along columns, inverse along rows (fused with r^T z).
+//
+// COCG (the conjugate-gradient recurrences with the unconjugated form u^T v,
+// which keep the complex symmetry of A and P^-1), per energy e:
+//   row  K1: p = z + beta p (p = z on the first iteration), w1 = row part of A p
+//   col  K2: w = w1 + column part of A p, partial sums of p^T w
+//        K3: alpha = rho / p^T w
+//   row  K4: x += alpha p, r -= alpha w, partial ||r||^2, s = FFT_x r
+//   col  K5: s = IFFT_y (FFT_y s / ((k_x^2 + k_y^2)/2 - E)) / (n_x n_y)
+//   row  K6: z = IFFT_x s, partial r^T z
+//        K7: convergence test on ||r||/||f||, beta = rho'/rho
+// Vectors are [nE][n_y][n_x] complex128; every kernel skips energies whose
+// state is not the one it works on.  Partial sums are reduced in a fixed order,
+// so results do not depend on scheduling.
+#include <algorithm>
+#include <cmath>
+
+#include "line_fft.hpp"
+#include "potential.hpp"
+#include "internal.hpp"
+
+namespace sofft {
+
+enum CocgState : int {
+  kActive = 0,     // iterating
+  kCheck = 1,      // recurrence residual below rtol: true residual pending
+  kDone = 2,       // true residual below rtol
+  kMaxit = 3,      // iteration limit reached
+  kBreakdown = 4,  // rho or p^T A p vanished twice in a row
+};
+
+struct CocgScalars {
+  cx<double> rho, alpha, beta;
+  double rr, ff, true_res;
+  int state, iters, first, restarts;
+};
+
+struct SseArgs {
+  int nx, ny, nE;
+  size_t vec;                  // n_x n_y
+  cx<double>* x;               // solution (caller's buffer)
+  cx<double>* r;
+  cx<double>* p;
+  cx<double>* w;
+  cx<double>* z;
+  cx<double>* s;               // preconditioner spectrum; also w1 of A p
+  const cx<double>* f;
+  int f_per_energy;
+  const cx<double>* V;         // U on the grid, [n_y][n_x]
+  const double* E;             // [nE]
+  CocgScalars* sc;             // [nE]
+  double* part_rr;             // [nE][nblk_row]
+  cx<double>* part_rz;         // [nE][nblk_row]
+  cx<double>* part_pw;         // [nE][nblk_col]
+  int nblk_row, nblk_col;
+  const cx<double>* twx;       // FFT stage twiddles along x and y
+  const cx<double>* twy;
+  double Lx, Ly;
+  int j0x, mx, j0y, my;        // ECS strips
+  const cx<double>* cx_strip;  // [C_{j,j-1} | C_{j,j} | C_{j,j+1}] on the x-strip
+  const cx<double>* cy_strip;
+  int lds_line_x, lds_line_y;
+};
+
+enum RowMode : int { kRowIter = 0, kRowTrue = 1 };          // K1: input p (updated) or x
+enum UpdMode : int { kUpdIter = 0, kUpdInit = 1, kUpdTrue = 2, kUpdCopy = 3 };
+
+__device__ __forceinline__ double kval(int e, int n, double L) {
+  const int m = e < n / 2 ? e : e - n;
+  return 6.283185307179586476925286766559 * double(m) / L;
+}
+
+__device__ __forceinline__ cx<double> shfl_xor(cx<double> v, int mask) {
+  return {__shfl_xor(v.re, mask), __shfl_xor(v.im, mask)};
+}
+
+// Sum over the block in a fixed order (wavefront butterflies, then the
+// wavefront sums in index order); result valid in thread 0.  red: LDS
+// scratch of blockDim.x/64 elements.  Contains block barriers.
+__device__ __forceinline__ cx<double> block_sum(cx<double> v, cx<double>* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = v + shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  cx<double> acc{0.0, 0.0};
+  if (threadIdx.x == 0)
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) acc = acc + red[w];
+  return acc;
+}
+
+// C applied on the strip of a line held in LDS (plain layout): element e's
+// row of C times the line, zero off the strip.
+__device__ __forceinline__ cx<double> c_apply(const LineLDS<double>& L, int e, int n, int j0, int m,
+                                              const cx<double>* cs) {
+  int p = e - j0;
+  if (p < 0) p += n;
+  if (p >= m) return {0.0, 0.0};
+  const int em = e == 0 ? n - 1 : e - 1, ep = e + 1 == n ? 0 : e + 1;
+  return cmul(cs[p], L[em]) + cmul(cs[m + p], L[e]) + cmul(cs[2 * m + p], L[ep]);
+}
+
+constexpr int kSseThreads = 1024;
+
+// ---------------------------------------------------------------- K1: row part of A v
+template <int N>
+__global__ void __launch_bounds__(kSseThreads) k_sse_row_mv(SseArgs a, int want, int mode) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
+  const int e = blockIdx.y;
+  CocgScalars& sc = a.sc[e];
+  if (sc.state != want) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<double>* lines = reinterpret_cast<cx<double>*>(smem);
+  const int lpb = blockDim.x / TPL;
+  const int l = threadIdx.x / TPL, t = threadIdx.x - l * TPL;
+  const int row = blockIdx.x * lpb + l;
+  const bool live = row < a.ny;
+  const int crow = live ? row : 0;
+  const LineLDS<double> L{lines, l * a.lds_line_x, 1};
+  const size_t off = size_t(e) * a.vec + size_t(crow) * N;
+  const double E = a.E[e];
+  cx<double> v[P], acc[P];
+  if (mode == kRowIter) {
+    const cx<double> beta = sc.beta;
+    const bool first = sc.first != 0;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const size_t i = off + t + TPL * s;
+      const cx<double> zz = live ? a.z[i] : cx<double>{0.0, 0.0};
+      v[s] = first ? zz : cfma(zz, beta, live ? a.p[i] : cx<double>{0.0, 0.0});
+      if (live) a.p[i] = v[s];
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = live ? a.x[off + t + TPL * s] : cx<double>{0.0, 0.0};
+  }
+  // C_x v + (U - E) v, with the line in LDS for the neighbours
+#pragma unroll
+  for (int s = 0; s < P; ++s) L[t + TPL * s] = v[s];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int el = t + TPL * s;
+    const cx<double> u = a.V[size_t(crow) * N + el] - cx<double>{E, 0.0};
+    acc[s] = cmul(u, v[s]);
+    if (a.mx > 0) acc[s] = acc[s] + c_apply(L, el, N, a.j0x, a.mx, a.cx_strip);
+  }
+  __syncthreads();
+  // T_x v = F_x^-1 (k_x^2/2) F_x v
+  fft<double, N, -1>(v, L, t, a.twx);
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const double k = kval(t + TPL * s, N, a.Lx);
+    v[s] = (0.5 * k * k / N) * v[s];
+  }
+  fft<double, N, +1>(v, L, t, a.twx);
+  if (live) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) a.s[off + t + TPL * s] = acc[s] + v[s];
+  }
+}
+
+__device__ __forceinline__ int xcd_block_sse(int b, int nblk) {
+  if (nblk % 8 != 0) return b;
+  return (b % 8) * (nblk / 8) + b / 8;
+}
+
+// ---------------------------------------------------------------- K2: column part of A v
+template <int N>
+__global__ void __launch_bounds__(kSseThreads) k_sse_col_mv(SseArgs a, int want, int mode) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
+  const int e = blockIdx.y;
+  CocgScalars& sc = a.sc[e];
+  if (sc.state != want) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<double>* lines = reinterpret_cast<cx<double>*>(smem);
+  const int lpb = blockDim.x / TPL;
+  const int c = threadIdx.x % lpb, t = threadIdx.x / lpb;
+  const int cb = xcd_block_sse(blockIdx.x, gridDim.x);
+  const int col = cb * lpb + c;
+  const bool live = col < a.nx;
+  const int ccol = live ? col : 0;
+  const LineLDS<double> L{lines, c, lpb};
+  const size_t base = size_t(e) * a.vec + ccol, ld = size_t(a.nx);
+  const cx<double>* in = mode == kRowIter ? a.p : a.x;
+  cx<double> v[P], acc[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const size_t i = base + size_t(t + TPL * s) * ld;
+    v[s] = live ? in[i] : cx<double>{0.0, 0.0};
+    acc[s] = live ? a.s[i] : cx<double>{0.0, 0.0};
+  }
+  if (a.my > 0) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) L[t + TPL * s] = v[s];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P; ++s) acc[s] = acc[s] + c_apply(L, t + TPL * s, N, a.j0y, a.my, a.cy_strip);
+    __syncthreads();
+  }
+  cx<double> pv[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) pv[s] = v[s];
+  fft<double, N, -1>(v, L, t, a.twy);
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const double k = kval(t + TPL * s, N, a.Ly);
+    v[s] = (0.5 * k * k / N) * v[s];
+  }
+  fft<double, N, +1>(v, L, t, a.twy);
+  cx<double> dot{0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const cx<double> wv = acc[s] + v[s];
+    if (live) {
+      a.w[base + size_t(t + TPL * s) * ld] = wv;
+      dot = cfma(dot, pv[s], wv);   // p^T w, unconjugated
+    }
+  }
+  if (mode == kRowIter) {
+    const cx<double> sum = block_sum(dot, lines);
+    if (threadIdx.x == 0) a.part_pw[size_t(e) * a.nblk_col + blockIdx.x] = sum;
+  }
+}
+
+// ---------------------------------------------------------------- K4: update and forward row FFT
+template <int N>
+__global__ void __launch_bounds__(kSseThreads) k_sse_row_upd(SseArgs a, int want, int mode) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
+  const int e = blockIdx.y;
+  CocgScalars& sc = a.sc[e];
+  if (sc.state != want) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<double>* lines = reinterpret_cast<cx<double>*>(smem);
+  const int lpb = blockDim.x / TPL;
+  const int l = threadIdx.x / TPL, t = threadIdx.x - l * TPL;
+  const int row = blockIdx.x * lpb + l;
+  const bool live = row < a.ny;
+  const int crow = live ? row : 0;
+  const LineLDS<double> L{lines, l * a.lds_line_x, 1};
+  const size_t off = size_t(e) * a.vec + size_t(crow) * N;
+  const size_t foff = (a.f_per_energy ? size_t(e) * a.vec : 0) + size_t(crow) * N;
+  cx<double> v[P];
+  double rr = 0.0;
+  const cx<double> alpha = sc.alpha;
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const size_t i = off + t + TPL * s;
+    cx<double> rv{0.0, 0.0};
+    if (live) {
+      if (mode == kUpdIter) {
+        a.x[i] = cfma(a.x[i], alpha, a.p[i]);
+        rv = a.r[i] - cmul(alpha, a.w[i]);
+      } else if (mode == kUpdInit) {
+        a.x[i] = cx<double>{0.0, 0.0};
+        rv = a.f[foff + t + TPL * s];
+      } else if (mode == kUpdTrue) {
+        rv = a.f[foff + t + TPL * s] - a.w[i];
+      } else {
+        rv = a.r[i];
+      }
+      if (mode != kUpdCopy) a.r[i] = rv;
+      rr += rv.re * rv.re + rv.im * rv.im;
+    }
+    v[s] = rv;
+  }
+  fft<double, N, -1>(v, L, t, a.twx);
+  if (live) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) a.s[off + t + TPL * s] = v[s];
+  }
+  const cx<double> sum = block_sum(cx<double>{rr, 0.0}, lines);
+  if (threadIdx.x == 0) a.part_rr[size_t(e) * a.nblk_row + blockIdx.x] = sum.re;
+}
+
+// ---------------------------------------------------------------- K5: column part of P^-1
+template <int N>
+__global__ void __launch_bounds__(kSseThreads) k_sse_col_prec(SseArgs a, int want) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
+  const int e = blockIdx.y;
+  if (a.sc[e].state != want) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<double>* lines = reinterpret_cast<cx<double>*>(smem);
+  const int lpb = blockDim.x / TPL;
+  const int c = threadIdx.x % lpb, t = threadIdx.x / lpb;
+  const int col = xcd_block_sse(blockIdx.x, gridDim.x) * lpb + c;
+  const bool live = col < a.nx;
+  const int ccol = live ? col : 0;
+  const LineLDS<double> L{lines, c, lpb};
+  const size_t base = size_t(e) * a.vec + ccol, ld = size_t(a.nx);
+  cx<double> v[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) v[s] = live ? a.s[base + size_t(t + TPL * s) * ld] : cx<double>{0.0, 0.0};
+  fft<double, N, -1>(v, L, t, a.twy);
+  const double kx = kval(ccol, a.nx, a.Lx), E = a.E[e];
+  const double scale = 1.0 / (double(a.nx) * double(N));
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const double ky = kval(t + TPL * s, N, a.Ly);
+    const double d = 0.5 * (kx * kx + ky * ky) - E;   // (K - E), as printed in Eq. PreconFFT
+    v[s] = (scale / d) * v[s];
+  }
+  fft<double, N, +1>(v, L, t, a.twy);
+  if (live) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) a.s[base + size_t(t + TPL * s) * ld] = v[s];
+  }
+}
+
+// ---------------------------------------------------------------- K6: inverse row FFT and r^T z
+template <int N>
+__global__ void __launch_bounds__(kSseThreads) k_sse_row_prec(SseArgs a, int want) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
+  const int e = blockIdx.y;
+  if (a.sc[e].state != want) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<double>* lines = reinterpret_cast<cx<double>*>(smem);
+  const int lpb = blockDim.x / TPL;
+  const int l = threadIdx.x / TPL, t = threadIdx.x - l * TPL;
+  const int row = blockIdx.x * lpb + l;
+  const bool live = row < a.ny;
+  const int crow = live ? row : 0;
+  const LineLDS<double> L{lines, l * a.lds_line_x, 1};
+  const size_t off = size_t(e) * a.vec + size_t(crow) * N;
+  cx<double> v[P], rv[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    v[s] = live ? a.s[off + t + TPL * s] : cx<double>{0.0, 0.0};
+    rv[s] = live ? a.r[off + t + TPL * s] : cx<double>{0.0, 0.0};
+  }
+  fft<double, N, +1>(v, L, t, a.twx);
+  cx<double> dot{0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    if (live) {
+      a.z[off + t + TPL * s] = v[s];
+      dot = cfma(dot, rv[s], v[s]);   // r^T z, unconjugated
+    }
+  }
+  const cx<double> sum = block_sum(dot, lines);
+  if (threadIdx.x == 0) a.part_rz[size_t(e) * a.nblk_row + blockIdx.x] = sum;
+}
+
+// ---------------------------------------------------------------- scalar steps (one thread per energy)
+__device__ __forceinline__ double cabs2(cx<double> v) { return v.re * v.re + v.im * v.im; }
+
+__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// After the initial r = f, z = P^-1 r: ||f||^2, rho = r^T z.
+__global__ void k_sse_init(SseArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nE) return;
+  CocgScalars& sc = a.sc[e];
+  double ff = 0.0;
+  cx<double> rz{0.0, 0.0};
+  for (int b = 0; b < a.nblk_row; ++b) {
+    ff += a.part_rr[size_t(e) * a.nblk_row + b];
+    rz = rz + a.part_rz[size_t(e) * a.nblk_row + b];
+  }
+  sc.ff = ff;
+  sc.rr = ff;
+  sc.rho = rz;
+  sc.first = 1;
+  sc.iters = 0;
+  sc.restarts = 0;
+  sc.true_res = 1.0;
+  sc.state = ff > 0.0 ? int(kActive) : int(kDone);
+  if (ff == 0.0) sc.true_res = 0.0;
+}
+
+// alpha = rho / p^T w.
+__global__ void k_sse_alpha(SseArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nE) return;
+  CocgScalars& sc = a.sc[e];
+  if (sc.state != kActive) return;
+  cx<double> pw{0.0, 0.0};
+  for (int b = 0; b < a.nblk_col; ++b) pw = pw + a.part_pw[size_t(e) * a.nblk_col + b];
+  if (cabs2(pw) == 0.0) {
+    sc.alpha = {0.0, 0.0};
+    sc.state = kBreakdown;
+    return;
+  }
+  sc.alpha = cdiv(sc.rho, pw);
+  sc.first = 0;
+}
+
+// Convergence test on the recurrence residual, then beta and rho.
+__global__ void k_sse_beta(SseArgs a, double rtol, int maxit) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nE) return;
+  CocgScalars& sc = a.sc[e];
+  if (sc.state != kActive) return;
+  double rr = 0.0;
+  cx<double> rz{0.0, 0.0};
+  for (int b = 0; b < a.nblk_row; ++b) {
+    rr += a.part_rr[size_t(e) * a.nblk_row + b];
+    rz = rz + a.part_rz[size_t(e) * a.nblk_row + b];
+  }
+  sc.rr = rr;
+  sc.iters += 1;
+  if (rr <= rtol * rtol * sc.ff) {
+    sc.state = kCheck;
+    return;
+  }
+  if (sc.iters >= maxit) {
+    sc.state = kMaxit;
+    sc.true_res = sqrt(rr / sc.ff);
+    return;
+  }
+  if (cabs2(sc.rho) == 0.0) {
+    sc.state = kBreakdown;
+    return;
+  }
+  sc.beta = cdiv(rz, sc.rho);
+  sc.rho = rz;
+}
+
+// After the true residual r = f - A x and z = P^-1 r of the energies that
+// passed the recurrence test: accept, or restart from the true residual.
+__global__ void k_sse_true(SseArgs a, double rtol, int maxit) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nE) return;
+  CocgScalars& sc = a.sc[e];
+  if (sc.state != kCheck) return;
+  double rr = 0.0;
+  cx<double> rz{0.0, 0.0};
+  for (int b = 0; b < a.nblk_row; ++b) {
+    rr += a.part_rr[size_t(e) * a.nblk_row + b];
+    rz = rz + a.part_rz[size_t(e) * a.nblk_row + b];
+  }
+  sc.true_res = sqrt(rr / sc.ff);
+  if (rr <= rtol * rtol * sc.ff) {
+    sc.state = kDone;
+  } else if (sc.iters >= maxit || sc.restarts >= 8) {
+    sc.state = kMaxit;
+  } else {
+    sc.rr = rr;
+    sc.rho = rz;
+    sc.first = 1;
+    sc.restarts += 1;
+    sc.state = kActive;
+  }
+}
+
+// U on the grid: soft-core at (z_x, z_y) plus field * x.
+__global__ void k_sse_potential(cx<double>* V, int nx, int ny, const cx<double>* zx, const cx<double>* zy,
+                                const double* x, double charge, double a2, double field) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= size_t(nx) * ny) return;
+  const int jx = int(i % nx), jy = int(i / nx);
+  const cx<double> s = cmul(zx[jx], zx[jx]) + cmul(zy[jy], zy[jy]) + cx<double>{a2, 0.0};
+  V[i] = potential_value(s, charge, field * x[jx]);
+}
+
+// ---------------------------------------------------------------- host side
+
+static int64_t sse_lds_elems(int64_t n) {
+  switch (n) {
+#define SOFFT_SSE_LDS(N) \
+  case N:                \
+    return fft_lds_elems<N>();
+    SOFFT_SSE_LDS(16) SOFFT_SSE_LDS(32) SOFFT_SSE_LDS(48) SOFFT_SSE_LDS(64) SOFFT_SSE_LDS(96)
+    SOFFT_SSE_LDS(128) SOFFT_SSE_LDS(192) SOFFT_SSE_LDS(256) SOFFT_SSE_LDS(384) SOFFT_SSE_LDS(512)
+    SOFFT_SSE_LDS(768) SOFFT_SSE_LDS(1024)
+#undef SOFFT_SSE_LDS
+    default:
+      return 2 * n;
+  }
+}
+
+template <typename K>
+static sofft_status sse_set_lds(K kernel, size_t bytes) {
+  static bool raised = false;
+  if (bytes > 65536 && !raised) {
+    SOFFT_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(150 * 1024)));
+    raised = true;
+  }
+  return SOFFT_OK;
+}
+
+enum SseKernel { kK1, kK2, kK4, kK5, kK6 };
+
+// Lines per block: up to 1024 threads (512 for the radix-3 shapes, which use
+// more registers) and within the LDS budget.
+static int sse_lpb(int64_t n, int lds_line) {
+  const ShapeInfo sh = shape_info(n);
+  const int tpl = int(n) / sh.P;
+  const int cap = sh.P == 4 ? kSseThreads : kSseThreads / 2;
+  int lpb = tpl >= cap ? 1 : cap / tpl;
+  while (lpb > 1 && size_t(lpb) * lds_line * sizeof(cx<double>) > size_t(150 * 1024)) --lpb;
+  return lpb;
+}
+
+template <int NX, int NY>
+static sofft_status sse_launch(SseKernel k, const SseArgs& a, int want, int mode, hipStream_t s, Timing& tm) {
+  constexpr int TPLX = NX / Shape<NX>::P, TPLY = NY / Shape<NY>::P;
+  const int lpbx = sse_lpb(NX, a.lds_line_x);
+  const int lpby = sse_lpb(NY, a.lds_line_y);
+  const size_t ldsx = size_t(lpbx) * a.lds_line_x * sizeof(cx<double>);
+  const size_t ldsy = size_t(lpby) * a.lds_line_y * sizeof(cx<double>);
+  const dim3 grow(a.nblk_row, a.nE), gcol(a.nblk_col, a.nE);
+  sofft_status st = SOFFT_OK;
+  switch (k) {
+    case kK1:
+      if ((st = sse_set_lds(k_sse_row_mv<NX>, ldsx)) != SOFFT_OK) return st;
+      if ((st = tm.begin(SOFFT_KERNEL_SSE_ROW_MV, s)) != SOFFT_OK) return st;
+      k_sse_row_mv<NX><<<grow, lpbx * TPLX, ldsx, s>>>(a, want, mode);
+      break;
+    case kK2:
+      if ((st = sse_set_lds(k_sse_col_mv<NY>, ldsy)) != SOFFT_OK) return st;
+      if ((st = tm.begin(SOFFT_KERNEL_SSE_COL_MV, s)) != SOFFT_OK) return st;
+      k_sse_col_mv<NY><<<gcol, lpby * TPLY, ldsy, s>>>(a, want, mode);
+      break;
+    case kK4:
+      if ((st = sse_set_lds(k_sse_row_upd<NX>, ldsx)) != SOFFT_OK) return st;
+      if ((st = tm.begin(SOFFT_KERNEL_SSE_ROW_UPD, s)) != SOFFT_OK) return st;
+      k_sse_row_upd<NX><<<grow, lpbx * TPLX, ldsx, s>>>(a, want, mode);
+      break;
+    case kK5:
+      if ((st = sse_set_lds(k_sse_col_prec<NY>, ldsy)) != SOFFT_OK) return st;
+      if ((st = tm.begin(SOFFT_KERNEL_SSE_COL_PREC, s)) != SOFFT_OK) return st;
+      k_sse_col_prec<NY><<<gcol, lpby * TPLY, ldsy, s>>>(a, want);
+      break;
+    case kK6:
+      if ((st = sse_set_lds(k_sse_row_prec<NX>, ldsx)) != SOFFT_OK) return st;
+      if ((st = tm.begin(SOFFT_KERNEL_SSE_ROW_PREC, s)) != SOFFT_OK) return st;
+      k_sse_row_prec<NX><<<grow, lpbx * TPLX, ldsx, s>>>(a, want);
+      break;
+  }
+  SOFFT_HIP_TRY(hipGetLastError());
+  return tm.end(s);
+}
+
+using SseLauncher = sofft_status (*)(SseKernel, const SseArgs&, int, int, hipStream_t, Timing&);
+
+// Square grids and the rectangular shapes the tests use; more pairs can be
+// added here.
+static SseLauncher sse_launcher(int64_t nx, int64_t ny) {
+#define SOFFT_SSE_PAIR(X, Y) \
+  if (nx == X && ny == Y) return sse_launch<X, Y>;
+  SOFFT_SSE_PAIR(16, 16) SOFFT_SSE_PAIR(32, 32) SOFFT_SSE_PAIR(64, 64) SOFFT_SSE_PAIR(128, 128)
+  SOFFT_SSE_PAIR(256, 256) SOFFT_SSE_PAIR(384, 384) SOFFT_SSE_PAIR(512, 512) SOFFT_SSE_PAIR(768, 768)
+  SOFFT_SSE_PAIR(1024, 1024) SOFFT_SSE_PAIR(64, 32) SOFFT_SSE_PAIR(32, 64) SOFFT_SSE_PAIR(128, 96)
+  SOFFT_SSE_PAIR(96, 128) SOFFT_SSE_PAIR(256, 128) SOFFT_SSE_PAIR(48, 64)
+#undef SOFFT_SSE_PAIR
+  return nullptr;
+}
+
+// Workspace: five vectors per energy, U on the grid, partial sums, scalars.
+static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipStream_t s) {
+  const Axis& X = p.ax[0];
+  const Axis& Y = p.ax[1];
+  const size_t vec = size_t(X.n) * Y.n;
+  const int llx = int(std::max<int64_t>(sse_lds_elems(X.n), 64));
+  const int lly = int(std::max<int64_t>(sse_lds_elems(Y.n), 64));
+  const int nbr = int((Y.n + sse_lpb(X.n, llx) - 1) / sse_lpb(X.n, llx));
+  const int nbc = int((X.n + sse_lpb(Y.n, lly) - 1) / sse_lpb(Y.n, lly));
+  const size_t bytes_vec = vec * sizeof(cx<double>);
+  const size_t need = 5 * bytes_vec * nE + bytes_vec + size_t(nE) * nbr * (sizeof(double) + sizeof(cx<double>)) +
+                      size_t(nE) * nbc * sizeof(cx<double>) + size_t(nE) * sizeof(CocgScalars) + 4096;
+  if (!p.sse_ws.p || p.sse_ws.bytes < need) {
+    dev_free(p.sse_ws);
+    if (hipMalloc(&p.sse_ws.p, need) != hipSuccess) {
+      p.sse_ws.p = nullptr;
+      set_error("hipMalloc of the solver workspace (" + std::to_string(need) + " bytes) failed");
+      return SOFFT_ENOMEM;
+    }
+    p.sse_ws.bytes = need;
+  }
+  char* q = static_cast<char*>(p.sse_ws.p);
+  auto take = [&](size_t b) {
+    char* r = q;
+    q += (b + 255) / 256 * 256;
+    return r;
+  };
+  a.nx = int(X.n);
+  a.ny = int(Y.n);
+  a.nE = nE;
+  a.vec = vec;
+  a.r = reinterpret_cast<cx<double>*>(take(bytes_vec * nE));
+  a.p = reinterpret_cast<cx<double>*>(take(bytes_vec * nE));
+  a.w = reinterpret_cast<cx<double>*>(take(bytes_vec * nE));
+  a.z = reinterpret_cast<cx<double>*>(take(bytes_vec * nE));
+  a.s = reinterpret_cast<cx<double>*>(take(bytes_vec * nE));
+  cx<double>* V = reinterpret_cast<cx<double>*>(take(bytes_vec));
+  a.V = V;
+  a.part_rr = reinterpret_cast<double*>(take(sizeof(double) * nE * nbr));
+  a.part_rz = reinterpret_cast<cx<double>*>(take(sizeof(cx<double>) * nE * nbr));
+  a.part_pw = reinterpret_cast<cx<double>*>(take(sizeof(cx<double>) * nE * nbc));
+  a.sc = reinterpret_cast<CocgScalars*>(take(sizeof(CocgScalars) * nE));
+  a.nblk_row = nbr;
+  a.nblk_col = nbc;
+  a.twx = static_cast<const cx<double>*>(X.tw64.p);
+  a.twy = static_cast<const cx<double>*>(Y.tw64.p);
+  a.Lx = X.L;
+  a.Ly = Y.L;
+  a.j0x = int(X.j0);
+  a.mx = int(X.m);
+  a.j0y = int(Y.j0);
+  a.my = int(Y.m);
+  a.cx_strip = static_cast<const cx<double>*>(X.cstrip64.p);
+  a.cy_strip = static_cast<const cx<double>*>(Y.cstrip64.p);
+  a.lds_line_x = llx;
+  a.lds_line_y = lly;
+  const int threads = 256;
+  k_sse_potential<<<int((vec + threads - 1) / threads), threads, 0, s>>>(
+      V, a.nx, a.ny, static_cast<const cx<double>*>(X.z_dev.p), static_cast<const cx<double>*>(Y.z_dev.p),
+      static_cast<const double*>(X.x_dev.p), p.prob.charge, p.prob.a2, field);
+  SOFFT_HIP_TRY(hipGetLastError());
+  return SOFFT_OK;
+}
+
+static sofft_status sse_check_plan(const Plan& p) {
+  if (p.prob.ndim != 2 || p.prob.dtype != SOFFT_C128) {
+    set_error("the stationary solver works on 2D complex128 plans");
+    return SOFFT_EUNSUPPORTED;
+  }
+  if (!sse_launcher(p.ax[0].n, p.ax[1].n)) {
+    set_error("no stationary-solver kernels for a " + std::to_string(p.ax[0].n) + " x " +
+              std::to_string(p.ax[1].n) + " grid");
+    return SOFFT_EUNSUPPORTED;
+  }
+  return SOFFT_OK;
+}
+
+sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E_host, int nE, double field,
+                       void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s) {
+  sofft_status st = sse_check_plan(p);
+  if (st != SOFFT_OK) return st;
+  SseArgs a{};
+  if ((st = sse_prepare(p, nE, field, a, s)) != SOFFT_OK) return st;
+  a.x = static_cast<cx<double>*>(x_out);
+  a.f = static_cast<const cx<double>*>(f);
+  a.f_per_energy = f_per_energy;
+  // energies
+  if (!p.sse_E.p || p.sse_E.bytes < sizeof(double) * nE) {
+    dev_free(p.sse_E);
+    if (hipMalloc(&p.sse_E.p, sizeof(double) * nE) != hipSuccess) {
+      p.sse_E.p = nullptr;
+      set_error("hipMalloc failed");
+      return SOFFT_ENOMEM;
+    }
+    p.sse_E.bytes = sizeof(double) * nE;
+  }
+  SOFFT_HIP_TRY(hipMemcpyAsync(p.sse_E.p, E_host, sizeof(double) * nE, hipMemcpyHostToDevice, s));
+  a.E = static_cast<const double*>(p.sse_E.p);
+  SseLauncher L = sse_launcher(p.ax[0].n, p.ax[1].n);
+  Timing& tm = p.timing;
+  const int sb = (nE + 63) / 64;
+  // r = f, x = 0, z = P^-1 r, rho = r^T z: run the set-up kernels on every
+  // energy by marking them active first.
+  std::vector<CocgScalars> init(nE);
+  for (auto& c : init) {
+    c = CocgScalars{};
+    c.state = kActive;
+  }
+  SOFFT_HIP_TRY(hipMemcpyAsync(a.sc, init.data(), sizeof(CocgScalars) * nE, hipMemcpyHostToDevice, s));
+  if ((st = L(kK4, a, kActive, kUpdInit, s, tm)) != SOFFT_OK) return st;
+  if ((st = L(kK5, a, kActive, 0, s, tm)) != SOFFT_OK) return st;
+  if ((st = L(kK6, a, kActive, 0, s, tm)) != SOFFT_OK) return st;
+  k_sse_init<<<sb, 64, 0, s>>>(a);
+  SOFFT_HIP_TRY(hipGetLastError());
+
+  std::vector<CocgScalars> host(nE);
+  const int poll = 4;
+  for (int round = 0;; ++round) {
+    // iterate until no energy is active
+    for (int it = 0;; ++it) {
+      if ((st = L(kK1, a, kActive, kRowIter, s, tm)) != SOFFT_OK) return st;
+      if ((st = L(kK2, a, kActive, kRowIter, s, tm)) != SOFFT_OK) return st;
+      k_sse_alpha<<<sb, 64, 0, s>>>(a);
+      SOFFT_HIP_TRY(hipGetLastError());
+      if ((st = L(kK4, a, kActive, kUpdIter, s, tm)) != SOFFT_OK) return st;
+      if ((st = L(kK5, a, kActive, 0, s, tm)) != SOFFT_OK) return st;
+      if ((st = L(kK6, a, kActive, 0, s, tm)) != SOFFT_OK) return st;
+      k_sse_beta<<<sb, 64, 0, s>>>(a, rtol, maxit);
+      SOFFT_HIP_TRY(hipGetLastError());
+      if ((it + 1) % poll == 0) {
+        SOFFT_HIP_TRY(hipMemcpyAsync(host.data(), a.sc, sizeof(CocgScalars) * nE, hipMemcpyDeviceToHost, s));
+        SOFFT_HIP_TRY(hipStreamSynchronize(s));
+        bool any = false;
+        for (const auto& c : host) any |= c.state == kActive;
+        if (!any) break;
+      }
+    }
+    // true residual of the energies that passed the recurrence test
+    if ((st = L(kK1, a, kCheck, kRowTrue, s, tm)) != SOFFT_OK) return st;
+    if ((st = L(kK2, a, kCheck, kRowTrue, s, tm)) != SOFFT_OK) return st;
+    if ((st = L(kK4, a, kCheck, kUpdTrue, s, tm)) != SOFFT_OK) return st;
+    if ((st = L(kK5, a, kCheck, 0, s, tm)) != SOFFT_OK) return st;
+    if ((st = L(kK6, a, kCheck, 0, s, tm)) != SOFFT_OK) return st;
+    k_sse_true<<<sb, 64, 0, s>>>(a, rtol, maxit);
+    SOFFT_HIP_TRY(hipGetLastError());
+    SOFFT_HIP_TRY(hipMemcpyAsync(host.data(), a.sc, sizeof(CocgScalars) * nE, hipMemcpyDeviceToHost, s));
+    SOFFT_HIP_TRY(hipStreamSynchronize(s));
+    bool any = false;
+    for (const auto& c : host) any |= c.state == kActive;
+    if (!any) break;
+  }
+  sofft_status worst = SOFFT_OK;
+  for (int e = 0; e < nE; ++e) {
+    const CocgScalars& c = host[e];
+    int code = SOFFT_OK;
+    if (c.state == kMaxit) code = SOFFT_NOT_CONVERGED;
+    if (c.state == kBreakdown) code = SOFFT_BREAKDOWN;
+    if (stats) {
+      stats[e].iterations = c.iters;
+      stats[e].status = code;
+      stats[e].rel_residual = c.state == kBreakdown ? std::sqrt(c.rr / c.ff) : c.true_res;
+      stats[e].restarts = c.restarts;
+    }
+    if (code != SOFFT_OK && worst == SOFFT_OK) worst = sofft_status(code);
+  }
+  return worst;
+}
+
+// w = A v (op 0) or w = P^-1 v (op 1) for one energy.
+sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s) {
+  sofft_status st = sse_check_plan(p);
+  if (st != SOFFT_OK) return st;
+  SseArgs a{};
+  if ((st = sse_prepare(p, 1, field, a, s)) != SOFFT_OK) return st;
+  if (!p.sse_E.p || p.sse_E.bytes < sizeof(double)) {
+    dev_free(p.sse_E);
+    if (hipMalloc(&p.sse_E.p, sizeof(double)) != hipSuccess) {
+      p.sse_E.p = nullptr;
+      set_error("hipMalloc failed");
+      return SOFFT_ENOMEM;
+    }
+    p.sse_E.bytes = sizeof(double);
+  }
+  SOFFT_HIP_TRY(hipMemcpyAsync(p.sse_E.p, &E, sizeof(double), hipMemcpyHostToDevice, s));
+  a.E = static_cast<const double*>(p.sse_E.p);
+  CocgScalars c{};
+  c.state = kActive;
+  SOFFT_HIP_TRY(hipMemcpyAsync(a.sc, &c, sizeof(c), hipMemcpyHostToDevice, s));
+  SseLauncher L = sse_launcher(p.ax[0].n, p.ax[1].n);
+  const size_t bytes = a.vec * sizeof(cx<double>);
+  if (op == 0) {
+    a.x = const_cast<cx<double>*>(static_cast<const cx<double>*>(v));
+    if ((st = L(kK1, a, kActive, kRowTrue, s, p.timing)) != SOFFT_OK) return st;
+    if ((st = L(kK2, a, kActive, kRowTrue, s, p.timing)) != SOFFT_OK) return st;
+    SOFFT_HIP_TRY(hipMemcpyAsync(w, a.w, bytes, hipMemcpyDeviceToDevice, s));
+  } else {
+    SOFFT_HIP_TRY(hipMemcpyAsync(a.r, v, bytes, hipMemcpyDeviceToDevice, s));
+    if ((st = L(kK4, a, kActive, kUpdCopy, s, p.timing)) != SOFFT_OK) return st;
+    if ((st = L(kK5, a, kActive, 0, s, p.timing)) != SOFFT_OK) return st;
+    if ((st = L(kK6, a, kActive, 0, s, p.timing)) != SOFFT_OK) return st;
+    SOFFT_HIP_TRY(hipMemcpyAsync(w, a.z, bytes, hipMemcpyDeviceToDevice, s));
+  }
+  return SOFFT_OK;
+}
+
+}  // namespace sofft

@@ -26,6 +26,16 @@ class SofftError(RuntimeError):
         self.code = code
 
 
+class SolveStats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("restarts", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
+        ("rel_residual", ctypes.c_double),
+    ]
+
+
 class Problem(ctypes.Structure):
     _fields_ = [
         ("ndim", ctypes.c_int32),
@@ -54,12 +64,18 @@ _SIGS = {
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_norm2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.c_void_p]),
+    "sofft_sse_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_sse_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_void_p]),
     "sofft_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sofft_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
 }
 
 KERNEL_ROW, KERNEL_COL, KERNEL_1D = 0, 1, 2
+KERNEL_SSE_ROW_MV, KERNEL_SSE_COL_MV, KERNEL_SSE_ROW_UPD, KERNEL_SSE_COL_PREC, KERNEL_SSE_ROW_PREC = 3, 4, 5, 6, 7
 
 
 def exported_symbols():
@@ -184,6 +200,36 @@ class Plan:
         cnt = ctypes.c_int64()
         _check(lib().sofft_timing_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
+
+    def sse_apply(self, op, v, E, field=0.0, out=None, stream=None):
+        """w = A v (op 0) or w = P^-1 v (op 1) at energy E (device tensors)."""
+        import torch
+        ptr = _dev_ptr(v, torch.complex128, self.numel, "v")
+        if out is None:
+            out = torch.empty_like(v)
+        optr = _dev_ptr(out, torch.complex128, self.numel, "out")
+        _check(lib().sofft_sse_apply(self._h, int(op), ptr, optr, float(E), float(field), _stream(stream)))
+        return out
+
+    def sse_solve(self, f, energies, field=0.0, rtol=1e-8, maxit=10000, out=None, stream=None):
+        """Solve (H - E_j) x_j = f for every energy; returns (x, stats, status).
+
+        f: complex128 device tensor [ny][nx] (shared) or [nE][ny][nx]."""
+        import torch
+        E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
+        nE = len(E)
+        per = 1 if f.numel() == nE * self.numel and nE > 1 else 0
+        fptr = _dev_ptr(f, torch.complex128, self.numel * (nE if per else 1), "f")
+        if out is None:
+            out = torch.empty((nE,) + self.shape, dtype=torch.complex128, device=f.device)
+        optr = _dev_ptr(out, torch.complex128, nE * self.numel, "out")
+        stats = (SolveStats * nE)()
+        code = lib().sofft_sse_solve(self._h, fptr, per, E.ctypes.data_as(ctypes.c_void_p), nE, float(field),
+                                     optr, float(rtol), int(maxit), stats, _stream(stream))
+        _check(code)
+        rows = [dict(iterations=s.iterations, status=s.status, restarts=s.restarts,
+                     rel_residual=s.rel_residual) for s in stats]
+        return out, rows, code
 
     def norm2(self, psi, stream=None):
         ptr = _dev_ptr(psi, self.torch_dtype, self.numel, "psi")
