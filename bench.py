@@ -68,6 +68,47 @@ def gpu_tdse(sofft, wl, torch, dtype, steps, warmup, seed=1):
     return dict(wall=wall, event_s=ev_s, kernels=kern, psi=result, npts=c.n * c.n)
 
 
+def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0):
+    """Batched COCG to 1e-8 on the 512^2 stationary workload (Sec. III)."""
+    c = wl.SSE_2D
+    plan = sofft.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=c.theta, charge=c.charge, a2=c.a2)
+    f = torch.from_numpy(-wl.smooth_source(c.n, c.n, seed=seed)).cuda()
+    E = c.energies() if n_energies is None else np.linspace(c.E_lo, c.E_hi, n_energies)
+    out = torch.empty((len(E), c.n, c.n), dtype=torch.complex128, device="cuda")
+    plan.sse_solve(f, E[:4], rtol=c.rtol, out=out[:4])       # warm-up (allocations, code load)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, stats, code = plan.sse_solve(f, E, rtol=c.rtol, out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.timing(True)
+    plan.sse_solve(f, E, rtol=c.rtol, out=out)
+    kinds = {"row_matvec": sofft.KERNEL_SSE_ROW_MV, "col_matvec": sofft.KERNEL_SSE_COL_MV,
+             "row_update_fft": sofft.KERNEL_SSE_ROW_UPD, "col_precond": sofft.KERNEL_SSE_COL_PREC,
+             "row_precond_dot": sofft.KERNEL_SSE_ROW_PREC}
+    kern = {k: plan.timing_read(v) for k, v in kinds.items()}
+    plan.timing(False)
+    plan.close()
+    its = np.array([s["iterations"] for s in stats])
+    res = np.array([s["rel_residual"] for s in stats])
+    npts = c.n * c.n
+    # algorithmic bytes of the fused passes per point per iteration and energy:
+    # K1 4S, K2 3S, K4 7S, K5 2S, K6 3S with S = 16 (complex128)
+    per_kernel_S = {"row_matvec": 4, "col_matvec": 3, "row_update_fft": 7, "col_precond": 2, "row_precond_dot": 3}
+    total_it = int(its.sum())
+    kern_s = sum(v[0] for v in kern.values()) / 1e3
+    alg_bytes = 19 * 16 * npts * total_it
+    dom = max(kern, key=lambda k: kern[k][0])
+    dom_bytes = per_kernel_S[dom] * 16 * npts * total_it
+    return {"time_to_tol_s": wall, "energies": int(len(E)), "grid": [c.n, c.n], "rtol": c.rtol,
+            "status": int(code), "iterations": {"min": int(its.min()), "mean": float(its.mean()),
+                                                 "max": int(its.max()), "total": total_it},
+            "max_true_rel_residual": float(res.max()),
+            "kernel_time_s": kern_s, "achieved_GBs_all_kernels": alg_bytes / kern_s / 1e9,
+            "dominant_kernel": dom, "dominant_GBs": dom_bytes / (kern[dom][0] / 1e3) / 1e9,
+            "kernels_ms": {k: v[0] for k, v in kern.items()}}
+
+
 def cpu_baseline(wl, sample_steps, seed=1):
     """The FP64 oracle on the host, a bounded sample of the same workload."""
     from oracle import tdse as ot
@@ -94,6 +135,10 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--pcg-energies", type=int, default=None)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -108,6 +153,14 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     sofft.lib()
+    if args.copy_mib:
+        a = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_mib} MiB x 5")
+        return
 
     log(f"TDSE 2D 1024^2 c128: warmup {args.warmup}, timed {args.steps} steps")
     r64 = gpu_tdse(sofft, wl, torch, sofft.C128, args.steps, args.warmup)
@@ -144,6 +197,14 @@ def main():
                 "rel_l2_vs_fp64_path": err, "steps": args.steps + args.warmup}
         log(f"  c64: {fp32['ms_per_step'] * 1e3:.1f} us/step, rel L2 vs FP64 path {err:.2e}")
 
+    pcg = None
+    if not args.no_pcg:
+        log("SSE 512^2 batched COCG to 1e-8")
+        pcg = gpu_pcg(sofft, wl, torch, args.pcg_energies)
+        log(f"  {pcg['energies']} energies in {pcg['time_to_tol_s']:.3f} s, iterations "
+            f"{pcg['iterations']['min']}..{pcg['iterations']['max']} (mean {pcg['iterations']['mean']:.0f}), "
+            f"{pcg['achieved_GBs_all_kernels']:.0f} GB/s over the fused passes")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"CPU oracle sample: {args.cpu_sample_steps} steps")
@@ -170,6 +231,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp32": fp32,
+        "pcg": pcg,
     }
     print(json.dumps(out), flush=True)
 
