@@ -28,6 +28,23 @@ METRIC = "grid-point SO-FFT steps/s + PCG time-to-1e-8 residual, plain vs learne
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs (profiles/), scaled by the copy-kernel calibration, or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tdse_2d_1024_c128_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    srcs = [os.path.join(ROOT, "paper_1505_06707_amd", "csrc", n)
+            for n in ("tdse.hip", "line_fft.hpp", "potential.hpp", "cx.hpp")]
+    sha = hashlib.sha256(b"".join(open(p, "rb").read() for p in srcs)).hexdigest()
+    if rec.get("kernel") != kernel or rec.get("source_sha256") != sha:
+        return None
+    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -178,7 +195,7 @@ def main():
     alg_bytes = 2 * 16 * npts
     achieved = alg_bytes / avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom), "kernel": dom,
                 "avg_launch_us": avg_s * 1e6, "launches": cnt,
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "kernels_avg_us": {k: v[0] / v[1] * 1e3 for k, v in kern.items() if v[1]}}
