@@ -38,6 +38,13 @@ __host__ __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {
 template <typename T>
 __host__ __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.im, a.re}; }
 
+// Precision changes between the storage type of a state (HBM, LDS) and the
+// FP64 arithmetic every kernel does.
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> narrow(cx<double> v) { return {T(v.re), T(v.im)}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<double> widen(cx<T> v) { return {double(v.re), double(v.im)}; }
+
 // ---------------------------------------------------------------- constexpr trig
 // Taylor series on [0, pi/4] with octant symmetry: about 1 ulp in double.
 namespace ct {

@@ -42,14 +42,15 @@ struct Axis {
   std::vector<zc> cdn, cdg, cup;  // C_{j,j-1}, C_{j,j}, C_{j,j+1}
   int64_t j0 = 0, m = 0;          // ECS strip: nodes (j0 + p) mod n, p < m
 
-  // Device tables that do not depend on dt (double and float copies).
-  DevBuf tw64, tw32, x_dev, z_dev, cstrip64;
+  // Device tables that do not depend on dt.  Every table is FP64: the
+  // complex64 state is also transformed and propagated in FP64 arithmetic.
+  DevBuf tw64, x_dev, z_dev, cstrip64;
   // Tables that depend on dt.
   double dt = 0;
   bool have_dt = false;
   int levels = 0;
-  DevBuf kin_full64, kin_half64, kin_full32, kin_half32;
-  DevBuf alpha64, gamma64, binv64, alpha32, gamma32, binv32;
+  DevBuf kin_full64, kin_half64;
+  DevBuf alpha64, gamma64, binv64;
 };
 
 // Optional per-launch event timing (measurement aid).

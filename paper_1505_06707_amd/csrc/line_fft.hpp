@@ -123,16 +123,23 @@ struct LineLDS {
   }
 };
 
-template <typename T, int SIGN>
-__device__ __forceinline__ cx<T> twiddle_mul(cx<T> a, cx<T> w) {
+template <int SIGN>
+__device__ __forceinline__ cx<double> twiddle_mul(cx<double> a, cx<double> w) {
   return SIGN < 0 ? cmul(a, w) : cmulc(a, w);
 }
 
+// The butterflies, twiddles and registers are FP64 for every state type; the
+// LDS exchange buffer has element type X (double, or float for a complex64
+// state, which then rounds once per stage output).  FP32 butterflies with
+// FP32 twiddles were measured to drift linearly with the number of time steps:
+// a rounded twiddle is the same operator error in every step, and adding its
+// residual after the rounded product does not remove it.
+
 // One rolled stage of radix RR with stride ns = R0 << sh (sh = log2(RR) (s-1));
-// tws points at this stage's twiddle table in LDS.
-template <typename T, int N, int SIGN, bool LAST>
-__device__ __forceinline__ void rolled_stage(cx<T> (&v)[Shape<N>::P], const LineLDS<T>& L, int t,
-                                             const cx<T>* __restrict__ tws, int sh) {
+// tws points at this stage's twiddle table.
+template <typename X, int N, int SIGN, bool LAST>
+__device__ __forceinline__ void rolled_stage(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, int t,
+                                             const cx<double>* __restrict__ tws, int sh) {
   constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, TPL = N / P, B = P / RR;
   constexpr int PAD = Shape<N>::PAD;
   const int ns = R0 << sh;
@@ -141,29 +148,28 @@ __device__ __forceinline__ void rolled_stage(cx<T> (&v)[Shape<N>::P], const Line
     const int j = t + TPL * b;
     const int q = (j >> sh) / R0;
     const int k = j - q * ns;
-    cx<T> a[RR];
+    cx<double> a[RR];
 #pragma unroll
     for (int m = 0; m < RR; ++m) a[m] = v[b + m * B];
 #pragma unroll
-    for (int m = 1; m < RR; ++m) a[m] = twiddle_mul<T, SIGN>(a[m], tws[(m - 1) * ns + k]);
-    DFT<RR, SIGN, T>::run(a);
+    for (int m = 1; m < RR; ++m) a[m] = twiddle_mul<SIGN>(a[m], tws[(m - 1) * ns + k]);
+    DFT<RR, SIGN, double>::run(a);
     if constexpr (LAST) {
 #pragma unroll
       for (int m = 0; m < RR; ++m) v[b + m * B] = a[m];
     } else {
       const int o = q * RR * ns + k;
 #pragma unroll
-      for (int m = 0; m < RR; ++m) L.template padded<PAD>(o + m * ns) = a[m];
+      for (int m = 0; m < RR; ++m) L.template padded<PAD>(o + m * ns) = narrow<X>(a[m]);
     }
   }
 }
 
 // In-place transform of the line held in v.  Every thread of the block must
-// call it (it contains block barriers); tw (the stage tables) must be visible
-// in LDS.
-template <typename T, int N, int SIGN>
-__device__ __forceinline__ void fft(cx<T> (&v)[Shape<N>::P], const LineLDS<T>& L, int t,
-                                    const cx<T>* __restrict__ tw) {
+// call it (it contains block barriers).
+template <typename X, int N, int SIGN>
+__device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, int t,
+                                    const cx<double>* __restrict__ tw) {
   constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, K = Shape<N>::K;
   constexpr int TPL = N / P, PAD = Shape<N>::PAD;
   constexpr int LR = RR == 4 ? 2 : (RR == 8 ? 3 : 4);   // log2(RR)
@@ -173,36 +179,36 @@ __device__ __forceinline__ void fft(cx<T> (&v)[Shape<N>::P], const LineLDS<T>& L
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const int j = t + TPL * b;
-      cx<T> a[R0];
+      cx<double> a[R0];
 #pragma unroll
       for (int m = 0; m < R0; ++m) a[m] = v[b + m * B];
-      DFT<R0, SIGN, T>::run(a);
+      DFT<R0, SIGN, double>::run(a);
 #pragma unroll
-      for (int m = 0; m < R0; ++m) L.template padded<PAD>(j * R0 + m) = a[m];
+      for (int m = 0; m < R0; ++m) L.template padded<PAD>(j * R0 + m) = narrow<X>(a[m]);
     }
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = L.template padded<PAD>(t + TPL * s);
+    for (int s = 0; s < P; ++s) v[s] = widen(L.template padded<PAD>(t + TPL * s));
     __syncthreads();
   }
   int off = 0;
 #pragma unroll 1
   for (int sh = 0; sh < LR * (K - 1); sh += LR) {
-    rolled_stage<T, N, SIGN, false>(v, L, t, tw + off, sh);
+    rolled_stage<X, N, SIGN, false>(v, L, t, tw + off, sh);
     off += (RR - 1) * (R0 << sh);
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = L.template padded<PAD>(t + TPL * s);
+    for (int s = 0; s < P; ++s) v[s] = widen(L.template padded<PAD>(t + TPL * s));
     __syncthreads();
   }
-  rolled_stage<T, N, SIGN, true>(v, L, t, tw + off, LR * (K - 1));
+  rolled_stage<X, N, SIGN, true>(v, L, t, tw + off, LR * (K - 1));
 }
 
-// Copy the stage twiddle tables (N - R0 entries) from global memory to LDS
-// (all threads of the block cooperate; a barrier must follow before use).
-template <typename T, int N>
-__device__ __forceinline__ void stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ src) {
-  for (int u = threadIdx.x; u < N - Shape<N>::R0; u += blockDim.x) dst[u] = src[u];
+// Copy the stage twiddle tables (N entries) from global memory to LDS (all
+// threads of the block cooperate; a barrier must follow).
+template <int N>
+__device__ __forceinline__ void stage_twiddles(cx<double>* dst, const cx<double>* __restrict__ src) {
+  for (int u = threadIdx.x; u < N; u += blockDim.x) dst[u] = src[u];
 }
 
 }  // namespace sofft

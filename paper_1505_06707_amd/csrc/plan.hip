@@ -173,7 +173,6 @@ sofft_status upload_static(Axis& a) {
     ns *= sh.RR;
   }
   auto t64 = to_cx<double>(tw);
-  auto t32 = to_cx<float>(tw);
   auto z64 = to_cx<double>(a.z);
   sofft_status st;
   // Rows of C on the strip, [C_{j,j-1} (m) | C_{j,j} (m) | C_{j,j+1} (m)] at
@@ -190,7 +189,6 @@ sofft_status upload_static(Axis& a) {
     if ((st = dev_upload(a.cstrip64, c64.data(), c64.size() * sizeof(c64[0]))) != SOFFT_OK) return st;
   }
   if ((st = dev_upload(a.tw64, t64.data(), t64.size() * sizeof(t64[0]))) != SOFFT_OK) return st;
-  if ((st = dev_upload(a.tw32, t32.data(), t32.size() * sizeof(t32[0]))) != SOFFT_OK) return st;
   if ((st = dev_upload(a.x_dev, a.x.data(), a.x.size() * sizeof(double))) != SOFFT_OK) return st;
   if ((st = dev_upload(a.z_dev, z64.data(), z64.size() * sizeof(z64[0]))) != SOFFT_OK) return st;
   return SOFFT_OK;
@@ -211,11 +209,8 @@ sofft_status ensure_dt(Axis& a, double dt) {
   sofft_status st;
   {
     auto f64 = to_cx<double>(kf), h64 = to_cx<double>(kh);
-    auto f32 = to_cx<float>(kf), h32 = to_cx<float>(kh);
     if ((st = dev_upload(a.kin_full64, f64.data(), n * sizeof(f64[0]))) != SOFFT_OK) return st;
     if ((st = dev_upload(a.kin_half64, h64.data(), n * sizeof(h64[0]))) != SOFFT_OK) return st;
-    if ((st = dev_upload(a.kin_full32, f32.data(), n * sizeof(f32[0]))) != SOFFT_OK) return st;
-    if ((st = dev_upload(a.kin_half32, h32.data(), n * sizeof(h32[0]))) != SOFFT_OK) return st;
   }
   // CN: y = (1 + i dt C/2)^-1 (1 - i dt C/2) v = 2 B^-1 v - v with B = 1 + i dt C/2.
   // B restricted to the strip is tridiagonal: a_p u_{p-1} + b_p u_p + c_p u_{p+1}.
@@ -259,13 +254,9 @@ sofft_status ensure_dt(Axis& a, double dt) {
     const auto& alv = levels ? al : dummy;
     const auto& gav = levels ? ga : dummy;
     auto al64 = to_cx<double>(alv), ga64 = to_cx<double>(gav), bi64 = to_cx<double>(bi);
-    auto al32 = to_cx<float>(alv), ga32 = to_cx<float>(gav), bi32 = to_cx<float>(bi);
     if ((st = dev_upload(a.alpha64, al64.data(), al64.size() * sizeof(al64[0]))) != SOFFT_OK) return st;
     if ((st = dev_upload(a.gamma64, ga64.data(), ga64.size() * sizeof(ga64[0]))) != SOFFT_OK) return st;
     if ((st = dev_upload(a.binv64, bi64.data(), bi64.size() * sizeof(bi64[0]))) != SOFFT_OK) return st;
-    if ((st = dev_upload(a.alpha32, al32.data(), al32.size() * sizeof(al32[0]))) != SOFFT_OK) return st;
-    if ((st = dev_upload(a.gamma32, ga32.data(), ga32.size() * sizeof(ga32[0]))) != SOFFT_OK) return st;
-    if ((st = dev_upload(a.binv32, bi32.data(), bi32.size() * sizeof(bi32[0]))) != SOFFT_OK) return st;
   }
   a.dt = dt;
   a.have_dt = true;
@@ -273,9 +264,8 @@ sofft_status ensure_dt(Axis& a, double dt) {
 }
 
 void free_axis(Axis& a) {
-  for (DevBuf* b : {&a.tw64, &a.tw32, &a.x_dev, &a.z_dev, &a.cstrip64, &a.kin_full64, &a.kin_half64,
-                    &a.kin_full32, &a.kin_half32, &a.alpha64, &a.gamma64, &a.binv64, &a.alpha32,
-                    &a.gamma32, &a.binv32})
+  for (DevBuf* b : {&a.tw64, &a.x_dev, &a.z_dev, &a.cstrip64, &a.kin_full64, &a.kin_half64, &a.alpha64,
+                    &a.gamma64, &a.binv64})
     dev_free(*b);
 }
 

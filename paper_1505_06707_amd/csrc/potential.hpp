@@ -71,19 +71,6 @@ __device__ __forceinline__ int strip_pos_rt(int e, int j0, int n) {
   return p < 0 ? p + n : p;
 }
 
-template <typename T>
-__device__ __forceinline__ cx<T> to(cx<double> v) {
-  return {T(v.re), T(v.im)};
-}
-
-// v * ph with the product formed in FP64 (phases are FP64; rounding them to
-// FP32 first would repeat the same rounding error every step).
-template <typename T>
-__device__ __forceinline__ cx<T> mul_phase(cx<T> v, cx<double> ph) {
-  const cx<double> r = cmul(cx<double>{double(v.re), double(v.im)}, ph);
-  return {T(r.re), T(r.im)};
-}
-
 // Position of element e on the ECS strip of its axis (>= m when outside).
 template <int N>
 __device__ __forceinline__ int strip_pos(int e, int j0) {

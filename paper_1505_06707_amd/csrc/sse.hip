@@ -499,9 +499,11 @@ static int sse_lpb(int64_t n, int lds_line) {
   const ShapeInfo sh = shape_info(n);
   const int tpl = int(n) / sh.P;
   const int cap = sh.P == 4 ? kSseThreads : kSseThreads / 2;
+  const int unit = tpl >= 64 ? 1 : 64 / tpl;   // whole wavefronts (block sums assume them)
   int lpb = tpl >= cap ? 1 : cap / tpl;
-  while (lpb > 1 && size_t(lpb) * lds_line * sizeof(cx<double>) > size_t(150 * 1024)) --lpb;
-  return lpb;
+  while (lpb > unit && size_t(lpb) * lds_line * sizeof(cx<double>) > size_t(150 * 1024)) --lpb;
+  lpb -= lpb % unit;
+  return lpb > 0 ? lpb : unit;
 }
 
 template <int NX, int NY>

@@ -16,12 +16,30 @@
 
 namespace sofft {
 
+// A complex128 or complex64 state (T = double or float) is loaded from HBM,
+// transformed and propagated in FP64 registers with FP64 tables, and rounded
+// to T only when stored.  Line exchanges and the CN reduction go through LDS
+// as xch_t<T>: double, or float for a complex64 state when built with
+// SOFFT_C64_LDS_FLOAT (half the LDS bytes, one more FP32 rounding per stage).
+template <typename T>
+struct Xch {
+  using type = double;
+};
+#if defined(SOFFT_C64_LDS_FLOAT)
+template <>
+struct Xch<float> {
+  using type = float;
+};
+#endif
+template <typename T>
+using xch_t = typename Xch<T>::type;
+
 template <typename T>
 struct PassArgs {
   cx<T>* psi;
   int nx, ny;
-  const cx<T>* tw;    // twiddles exp(-2 pi i u/n) of the pass axis
-  const cx<T>* kin;   // kinetic phase (with 1/n) of the pass axis
+  const cx<double>* tw;    // twiddles exp(-2 pi i u/n) of the pass axis
+  const cx<double>* kin;   // kinetic phase (with 1/n) of the pass axis
   int do_pot;         // apply the potential half-step and the CN sweep
   const double* f_mid;
   int64_t step;
@@ -32,10 +50,10 @@ struct PassArgs {
   const cx<double>* zy;   // z(y_j) (2D) or null
   int j0, m, levels;      // ECS strip of the pass axis
   int j0y, my;            // ECS strip of the y axis (row pass of a 2D grid)
-  const cx<T>* alpha;
-  const cx<T>* gamma;
-  const cx<T>* binv;
-  int lds_line;           // LDS elements reserved per line
+  const cx<double>* alpha;
+  const cx<double>* gamma;
+  const cx<double>* binv;
+  int lds_line;           // LDS elements (of xch_t<T>) reserved per line
 };
 
 // Crank-Nicolson on the ECS strip of a line held by the whole block (1D):
@@ -43,8 +61,8 @@ struct PassArgs {
 // storage (buffers [0, m) and [m, 2m)).  As in pcr_wave, neighbours are read at
 // clamped indices (the host zeroes the coefficients that reach past the strip)
 // and the next level's coefficients are fetched during the current level.
-template <typename T, int N>
-__device__ __forceinline__ void cn_strip(cx<T> (&v)[Shape<N>::P], const LineLDS<T>& L, int t,
+template <typename T, int N, typename X>
+__device__ __forceinline__ void cn_strip(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, int t,
                                          const PassArgs<T>& a) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   constexpr int MAXPOS = P / 2;   // strip positions per thread: the host keeps m <= N/2
@@ -52,9 +70,9 @@ __device__ __forceinline__ void cn_strip(cx<T> (&v)[Shape<N>::P], const LineLDS<
 #pragma unroll
   for (int s = 0; s < P; ++s) {
     const int p = strip_pos<N>(t + TPL * s, a.j0);
-    if (p < m) L[p] = v[s];
+    if (p < m) L[p] = narrow<X>(v[s]);
   }
-  cx<T> al[MAXPOS], ga[MAXPOS];
+  cx<double> al[MAXPOS], ga[MAXPOS];
   if (a.levels > 0) {
 #pragma unroll
     for (int i = 0; i < MAXPOS; ++i) {
@@ -67,15 +85,16 @@ __device__ __forceinline__ void cn_strip(cx<T> (&v)[Shape<N>::P], const LineLDS<
   int src = 0, dst = m;
   for (int l = 0; l < a.levels; ++l) {
     const int st = 1 << l;
-    const cx<T>* aln = a.alpha + size_t(l + 1 < a.levels ? l + 1 : l) * m;
-    const cx<T>* gan = a.gamma + size_t(l + 1 < a.levels ? l + 1 : l) * m;
+    const cx<double>* aln = a.alpha + size_t(l + 1 < a.levels ? l + 1 : l) * m;
+    const cx<double>* gan = a.gamma + size_t(l + 1 < a.levels ? l + 1 : l) * m;
 #pragma unroll
     for (int i = 0; i < MAXPOS; ++i) {
       const int p0 = t + TPL * i, p = min(p0, m - 1);
-      const cx<T> d = L[src + p] - cmul(al[i], L[src + max(p - st, 0)]) - cmul(ga[i], L[src + min(p + st, m - 1)]);
+      const cx<double> d = widen(L[src + p]) - cmul(al[i], widen(L[src + max(p - st, 0)])) -
+                           cmul(ga[i], widen(L[src + min(p + st, m - 1)]));
       al[i] = aln[p];
       ga[i] = gan[p];
-      if (p0 < m) L[dst + p] = d;
+      if (p0 < m) L[dst + p] = narrow<X>(d);
     }
     __syncthreads();
     const int tmp = src;
@@ -85,18 +104,20 @@ __device__ __forceinline__ void cn_strip(cx<T> (&v)[Shape<N>::P], const LineLDS<
 #pragma unroll
   for (int s = 0; s < P; ++s) {
     const int p = strip_pos<N>(t + TPL * s, a.j0);
-    if (p < m) v[s] = T(2) * cmul(a.binv[p], L[src + p]) - v[s];
+    if (p < m) v[s] = 2.0 * cmul(a.binv[p], widen(L[src + p])) - v[s];
   }
   __syncthreads();
 }
 
-// U/2 . C . U/2 along a line whose cross coordinate is fixed (1D, or a 2D row
-// outside the y-strip): outside the strip the two half-steps are one multiply
-// by the squared phase; on the strip the phase is parked in LDS (from 2m)
-// across the CN.  With both_halves false only the first half-step and C apply.
-template <typename T, int N, typename PhaseFn>
-__device__ __forceinline__ void pot_cn_pot(cx<T> (&v)[Shape<N>::P], const LineLDS<T>& L, int t,
-                                           const PassArgs<T>& a, bool both_halves, PhaseFn phase) {
+// U/2 . C . U/2 along a line whose cross coordinate is fixed (1D): outside
+// the strip the two half-steps are one multiply by the squared phase; on the
+// strip the phase is parked in LDS (from 2m) across the CN when the exchange
+// type is FP64, and evaluated again after it otherwise (an FP32 copy would be
+// the same rounding error in every step).
+template <typename T, int N, typename X, typename PhaseFn>
+__device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, int t,
+                                           const PassArgs<T>& a, PhaseFn phase) {
+  constexpr bool park = std::is_same<X, double>::value;
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int m = a.m;
 #pragma unroll
@@ -105,29 +126,34 @@ __device__ __forceinline__ void pot_cn_pot(cx<T> (&v)[Shape<N>::P], const LineLD
     const cx<double> ph = phase(e);
     const int p = strip_pos<N>(e, a.j0);
     if (p < m) {
-      v[s] = mul_phase(v[s], ph);
-      if (both_halves) L[2 * m + p] = to<T>(ph);
+      v[s] = cmul(v[s], ph);
+      if constexpr (park) L[2 * m + p] = ph;
     } else {
-      v[s] = mul_phase(v[s], both_halves ? cmul(ph, ph) : ph);
+      v[s] = cmul(v[s], cmul(ph, ph));
     }
   }
   if (m > 0) {
     cn_strip<T, N>(v, L, t, a);
-    if (both_halves) {
 #pragma unroll
-      for (int s = 0; s < P; ++s) {
-        const int p = strip_pos<N>(t + TPL * s, a.j0);
-        if (p < m) v[s] = cmul(v[s], L[2 * m + p]);
+    for (int s = 0; s < P; ++s) {
+      const int e = t + TPL * s;
+      const int p = strip_pos<N>(e, a.j0);
+      if (p < m) {
+        if constexpr (park) {
+          v[s] = cmul(v[s], widen(L[2 * m + p]));
+        } else {
+          v[s] = cmul(v[s], phase(e));
+        }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
-// Blocks of the 2D passes have 256 threads (one 1024-point line, or several
-// shorter ones), so that several independent blocks share a CU and one
-// block's barriers overlap another's work.  P = 4 shapes keep <= 128 VGPRs
-// (4 waves per SIMD); P = 12 shapes (radix 3) need more and run 2.
+// Blocks of the 2D passes have 1024 threads (four 1024-point lines, or more
+// shorter ones) for P = 4 shapes, which then keep <= 128 VGPRs (4 waves per
+// SIMD), and 512 threads for P = 12 shapes (radix 3), which need more
+// registers and run 2 waves per SIMD.
 #ifndef SOFFT_ROW_THREADS
 #define SOFFT_ROW_THREADS 1024
 #endif
@@ -140,9 +166,12 @@ template <int N>
 constexpr int min_waves_per_simd() {
   return Shape<N>::P == 4 ? 4 : 2;
 }
+// Threads per block: THREADS (P = 12 shapes at most 512, so that two waves
+// per SIMD leave them 256 VGPRs), and at least one whole line.
 template <int N, int THREADS>
-constexpr int block_threads() {   // at least one whole line
-  return N / Shape<N>::P > THREADS ? N / Shape<N>::P : THREADS;
+constexpr int block_threads() {
+  constexpr int cap = Shape<N>::P == 4 ? THREADS : (THREADS < 512 ? THREADS : 512);
+  return N / Shape<N>::P > cap ? N / Shape<N>::P : cap;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -161,12 +190,12 @@ __device__ __forceinline__ void wave_sync() {
 constexpr int kPcrPos = 4;
 __host__ __device__ __forceinline__ int cn_result(int m, int levels) { return (levels & 1) ? 0 : m; }
 
-template <typename T, int N>
-__device__ __forceinline__ void pcr_wave(const LineLDS<T>& Lw, int lane, const PassArgs<T>& a) {
+template <typename T, int N, typename X>
+__device__ __forceinline__ void pcr_wave(const LineLDS<X>& Lw, int lane, const PassArgs<T>& a) {
   constexpr int W = N / 128 > 0 ? (N / 128 < kPcrPos ? N / 128 : kPcrPos) : 1;
   const int m = a.m, levels = a.levels;
   int src = 0, dst = m;
-  cx<T> al[W], ga[W];
+  cx<double> al[W], ga[W];
 #pragma unroll
   for (int i = 0; i < W; ++i) {
     const int p = min(lane + 64 * i, m - 1);
@@ -177,15 +206,16 @@ __device__ __forceinline__ void pcr_wave(const LineLDS<T>& Lw, int lane, const P
   }
   for (int l = 0; l < levels; ++l) {
     const int st = 1 << l;
-    const cx<T>* aln = a.alpha + size_t(l + 1 < levels ? l + 1 : l) * m;
-    const cx<T>* gan = a.gamma + size_t(l + 1 < levels ? l + 1 : l) * m;
+    const cx<double>* aln = a.alpha + size_t(l + 1 < levels ? l + 1 : l) * m;
+    const cx<double>* gan = a.gamma + size_t(l + 1 < levels ? l + 1 : l) * m;
 #pragma unroll
     for (int i = 0; i < W; ++i) {
       const int p0 = lane + 64 * i, p = min(p0, m - 1);
-      const cx<T> d = Lw[src + p] - cmul(al[i], Lw[src + max(p - st, 0)]) - cmul(ga[i], Lw[src + min(p + st, m - 1)]);
+      const cx<double> d = widen(Lw[src + p]) - cmul(al[i], widen(Lw[src + max(p - st, 0)])) -
+                           cmul(ga[i], widen(Lw[src + min(p + st, m - 1)]));
       al[i] = aln[p];
       ga[i] = gan[p];
-      if (p0 < m) Lw[dst + p] = d;
+      if (p0 < m) Lw[dst + p] = narrow<X>(d);
     }
     wave_sync();
     const int tmp = src;
@@ -195,8 +225,8 @@ __device__ __forceinline__ void pcr_wave(const LineLDS<T>& Lw, int lane, const P
 #pragma unroll
   for (int i = 0; i < W; ++i) {
     const int p0 = lane + 64 * i, p = min(p0, m - 1);
-    const cx<T> u = cmul(a.binv[p], Lw[src + p]);
-    if (p0 < m) Lw[dst + p] = u;
+    const cx<double> u = cmul(a.binv[p], widen(Lw[src + p]));
+    if (p0 < m) Lw[dst + p] = narrow<X>(u);
   }
 }
 
@@ -206,7 +236,7 @@ __device__ __forceinline__ void pcr_wave(const LineLDS<T>& Lw, int lane, const P
 template <typename T, int N, typename LineOf>
 __device__ __forceinline__ void cn_block(int lpb, const PassArgs<T>& a, LineOf line_of) {
   __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;   // whole wavefronts
   for (int ln = w; ln < lpb; ln += nw) pcr_wave<T, N>(line_of(ln), lane, a);
   __syncthreads();
 }
@@ -216,20 +246,23 @@ __device__ __forceinline__ void cn_block(int lpb, const PassArgs<T>& a, LineOf l
 // coefficients are read from global memory (they stay in the vector L1).
 template <typename T, int N>
 __global__ void __launch_bounds__((block_threads<N, kRowThreads>()), min_waves_per_simd<N>()) k_row_pass(PassArgs<T> a) {
+  using X = xch_t<T>;
+  constexpr bool park = std::is_same<X, double>::value;
   constexpr int P = Shape<N>::P, TPL = N / P;
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<T>* lines = reinterpret_cast<cx<T>*>(smem);
+  cx<X>* lines = reinterpret_cast<cx<X>*>(smem);
   const int lpb = blockDim.x / TPL;
   const int l = threadIdx.x / TPL, t = threadIdx.x - l * TPL;
   const int row = blockIdx.x * lpb + l;
   const bool live = row < a.ny;
   const int crow = live ? row : 0;
-  const LineLDS<T> L{lines, l * a.lds_line, 1};
+  const LineLDS<X> L{lines, l * a.lds_line, 1};
   cx<T>* line = a.psi + size_t(crow) * N;
   const bool cn = a.do_pot && a.m > 0;
-  cx<T> v[P], kin[P];
+  cx<double> v[P];
+  cx<double> kin[P];
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = live ? line[t + TPL * s] : cx<T>{T(0), T(0)};
+  for (int s = 0; s < P; ++s) v[s] = live ? widen(line[t + TPL * s]) : cx<double>{0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
   // inputs of the potential, fetched before the transforms
@@ -246,14 +279,15 @@ __global__ void __launch_bounds__((block_threads<N, kRowThreads>()), min_waves_p
     f = a.f_mid ? a.f_mid[a.step] : 0.0;
     if (a.zy) zy = a.zy[crow];
   }
-  fft<T, N, -1>(v, L, t, a.tw);
+  fft<X, N, -1>(v, L, t, a.tw);
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
-  fft<T, N, +1>(v, L, t, a.tw);
+  fft<X, N, +1>(v, L, t, a.tw);
   if (a.do_pot) {
     // Rows outside the y-strip get both potential half-steps here (C_y is the
     // identity on them); rows on it get the first, the column pass the second.
-    // On the x-strip the phase waits in LDS (from 2m) across the CN.
+    // On the x-strip the phase waits in LDS (from 2m) across the CN, or is
+    // evaluated again after it when LDS holds FP32.
     const cx<double> zy2a = cmul(zy, zy) + cx<double>{a.a2, 0.0};
     const bool both = strip_pos_rt(crow, a.j0y, a.ny) >= a.my;
     const int m = a.m;
@@ -262,28 +296,36 @@ __global__ void __launch_bounds__((block_threads<N, kRowThreads>()), min_waves_p
       const cx<double> ph = potential_phase(cmul(zxs[s], zxs[s]) + zy2a, a.charge, f * xs[s], a.ht);
       const int p = strip_pos<N>(t + TPL * s, a.j0);
       if (p < m) {
-        v[s] = mul_phase(v[s], ph);
-        L[p] = v[s];
-        if (both) L[2 * m + p] = to<T>(ph);
+        v[s] = cmul(v[s], ph);
+        L[p] = narrow<X>(v[s]);
+        if constexpr (park) {
+          if (both) L[2 * m + p] = ph;
+        }
       } else {
-        v[s] = mul_phase(v[s], both ? cmul(ph, ph) : ph);
+        v[s] = cmul(v[s], both ? cmul(ph, ph) : ph);
       }
     }
     if (cn) {
-      cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<T>{lines, ln * a.lds_line, 1}; });
+      cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln * a.lds_line, 1}; });
 #pragma unroll
       for (int s = 0; s < P; ++s) {
         const int p = strip_pos<N>(t + TPL * s, a.j0);
         if (p < m) {
-          v[s] = T(2) * L[cn_result(m, a.levels) + p] - v[s];
-          if (both) v[s] = cmul(v[s], L[2 * m + p]);
+          v[s] = 2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s];
+          if (both) {
+            if constexpr (park) {
+              v[s] = cmul(v[s], widen(L[2 * m + p]));
+            } else {
+              v[s] = cmul(v[s], potential_phase(cmul(zxs[s], zxs[s]) + zy2a, a.charge, f * xs[s], a.ht));
+            }
+          }
         }
       }
     }
   }
   if (live) {
 #pragma unroll
-    for (int s = 0; s < P; ++s) line[t + TPL * s] = v[s];
+    for (int s = 0; s < P; ++s) line[t + TPL * s] = narrow<T>(v[s]);
   }
 }
 
@@ -297,21 +339,23 @@ __device__ __forceinline__ int xcd_block(int b, int nblk) {
 
 template <typename T, int N>
 __global__ void __launch_bounds__((block_threads<N, kColThreads>()), min_waves_per_simd<N>()) k_col_pass(PassArgs<T> a) {
+  using X = xch_t<T>;
   constexpr int P = Shape<N>::P, TPL = N / P;
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<T>* lines = reinterpret_cast<cx<T>*>(smem);
+  cx<X>* lines = reinterpret_cast<cx<X>*>(smem);
   const int lpb = blockDim.x / TPL;
   const int c = threadIdx.x % lpb, t = threadIdx.x / lpb;
   const int col = xcd_block(blockIdx.x, gridDim.x) * lpb + c;
   const bool live = col < a.nx;
   const int ccol = live ? col : 0;
-  const LineLDS<T> L{lines, c, lpb};
+  const LineLDS<X> L{lines, c, lpb};
   cx<T>* base = a.psi + ccol;
   const size_t ld = size_t(a.nx);
   const bool cn = a.do_pot && a.m > 0;
-  cx<T> v[P], kin[P];
+  cx<double> v[P];
+  cx<double> kin[P];
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = live ? base[size_t(t + TPL * s) * ld] : cx<T>{T(0), T(0)};
+  for (int s = 0; s < P; ++s) v[s] = live ? widen(base[size_t(t + TPL * s) * ld]) : cx<double>{0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
   if (cn) {
@@ -323,9 +367,9 @@ __global__ void __launch_bounds__((block_threads<N, kColThreads>()), min_waves_p
 #pragma unroll
     for (int s = 0; s < P; ++s) {
       const int p = strip_pos<N>(t + TPL * s, a.j0);
-      if (p < m) L[p] = v[s];
+      if (p < m) L[p] = narrow<X>(v[s]);
     }
-    cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<T>{lines, ln, lpb}; });
+    cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln, lpb}; });
     const cx<double> zx2a = cmul(zx, zx) + cx<double>{a.a2, 0.0};
 #pragma unroll
     for (int s = 0; s < P; ++s) {
@@ -333,58 +377,60 @@ __global__ void __launch_bounds__((block_threads<N, kColThreads>()), min_waves_p
       const int p = strip_pos<N>(e, a.j0);
       if (p < m) {
         const cx<double> zy = a.zy[e];
-        v[s] = mul_phase(T(2) * L[cn_result(m, a.levels) + p] - v[s],
-                         potential_phase(zx2a + cmul(zy, zy), a.charge, fx, a.ht));
+        v[s] = cmul(2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s],
+                    potential_phase(zx2a + cmul(zy, zy), a.charge, fx, a.ht));
       }
     }
     __syncthreads();
   }
-  fft<T, N, -1>(v, L, t, a.tw);
+  fft<X, N, -1>(v, L, t, a.tw);
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
-  fft<T, N, +1>(v, L, t, a.tw);
+  fft<X, N, +1>(v, L, t, a.tw);
   if (live) {
 #pragma unroll
-    for (int s = 0; s < P; ++s) base[size_t(t + TPL * s) * ld] = v[s];
+    for (int s = 0; s < P; ++s) base[size_t(t + TPL * s) * ld] = narrow<T>(v[s]);
   }
 }
 
 // 1D: the whole propagation in one workgroup; psi stays in registers.
 template <typename T, int N>
-__global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const cx<T>* kin_half,
-                                                             const cx<T>* kin_full, int64_t nsteps) {
+__global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const cx<double>* kin_half,
+                                                             const cx<double>* kin_full, int64_t nsteps) {
+  using X = xch_t<T>;
   constexpr int P = Shape<N>::P, TPL = N / P;
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
+  cx<double>* tw = reinterpret_cast<cx<double>*>(smem);   // [twiddles: N][line]
   const int t = threadIdx.x;
-  const LineLDS<T> L{tw + N, 0, 1};
-  cx<T> v[P], kf[P];
+  const LineLDS<X> L{reinterpret_cast<cx<X>*>(tw + N), 0, 1};
+  cx<double> v[P];
+  cx<double> kf[P];
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = a.psi[t + TPL * s];
+  for (int s = 0; s < P; ++s) v[s] = widen(a.psi[t + TPL * s]);
 #pragma unroll
   for (int s = 0; s < P; ++s) kf[s] = kin_half[t + TPL * s];
-  stage_twiddles<T, N>(tw, a.tw);
+  stage_twiddles<N>(tw, a.tw);
   __syncthreads();
-  fft<T, N, -1>(v, L, t, tw);
+  fft<X, N, -1>(v, L, t, tw);
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kf[s]);
-  fft<T, N, +1>(v, L, t, tw);
+  fft<X, N, +1>(v, L, t, tw);
   for (int64_t n = 0; n < nsteps; ++n) {
     const double f = a.f_mid ? a.f_mid[n] : 0.0;
-    pot_cn_pot<T, N>(v, L, t, a, true, [&](int e) {
+    pot_cn_pot<T, N>(v, L, t, a, [&](int e) {
       const cx<double> z = a.zx[e];
       return potential_phase(cmul(z, z) + cx<double>{a.a2, 0.0}, a.charge, f * a.x[e], a.ht);
     });
-    const cx<T>* kin = n + 1 == nsteps ? kin_half : kin_full;
+    const cx<double>* kin = n + 1 == nsteps ? kin_half : kin_full;
 #pragma unroll
     for (int s = 0; s < P; ++s) kf[s] = kin[t + TPL * s];
-    fft<T, N, -1>(v, L, t, tw);
+    fft<X, N, -1>(v, L, t, tw);
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kf[s]);
-    fft<T, N, +1>(v, L, t, tw);
+    fft<X, N, +1>(v, L, t, tw);
   }
 #pragma unroll
-  for (int s = 0; s < P; ++s) a.psi[t + TPL * s] = v[s];
+  for (int s = 0; s < P; ++s) a.psi[t + TPL * s] = narrow<T>(v[s]);
 }
 
 template <typename T>
@@ -405,11 +451,6 @@ __global__ void __launch_bounds__(256) k_norm2(const cx<T>* psi, int64_t n, doub
 }
 
 // ---------------------------------------------------------------- launchers
-
-template <typename T>
-static const cx<T>* tab(const DevBuf& b64, const DevBuf& b32) {
-  return static_cast<const cx<T>*>(std::is_same<T, double>::value ? b64.p : b32.p);
-}
 
 static int64_t lds_elems_for(int64_t n) {
   switch (n) {
@@ -432,7 +473,7 @@ static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   a.psi = static_cast<cx<T>*>(psi);
   a.nx = int(p.ax[0].n);
   a.ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
-  a.tw = tab<T>(A.tw64, A.tw32);
+  a.tw = static_cast<const cx<double>*>(A.tw64.p);
   a.ht = 0.5 * dt;
   a.charge = p.prob.charge;
   a.a2 = p.prob.a2;
@@ -442,9 +483,9 @@ static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   a.j0 = int(A.j0);
   a.m = int(A.m);
   a.levels = A.levels;
-  a.alpha = tab<T>(A.alpha64, A.alpha32);
-  a.gamma = tab<T>(A.gamma64, A.gamma32);
-  a.binv = tab<T>(A.binv64, A.binv32);
+  a.alpha = static_cast<const cx<double>*>(A.alpha64.p);
+  a.gamma = static_cast<const cx<double>*>(A.gamma64.p);
+  a.binv = static_cast<const cx<double>*>(A.binv64.p);
   a.lds_line = int(std::max<int64_t>(lds_elems_for(A.n), 3 * A.m));
   // y-strip, used by the row pass to decide which rows take both half-steps
   a.j0y = p.prob.ndim == 2 ? int(p.ax[1].j0) : 0;
@@ -485,13 +526,21 @@ static sofft_status set_lds(K kernel, size_t bytes) {
     default: break;                               \
   }
 
-// Lines per block of a 2D pass with THREADS threads per block (at least one).
+// Lines per block of a 2D pass: THREADS threads' worth (at least one line),
+// fewer when the lines' LDS would exceed the budget.
+// Blocks are whole wavefronts (the CN gives each wavefront whole lines), so
+// with lines shorter than a wavefront lpb is a multiple of 64/TPL.
 template <typename T, int N, int THREADS>
 static int lines_per_block(int lds_line, size_t* lds_bytes) {
   constexpr int TPL = N / Shape<N>::P;
-  const int lpb = TPL >= THREADS ? 1 : THREADS / TPL;
-  *lds_bytes = size_t(lpb) * lds_line * sizeof(cx<T>);
-  return *lds_bytes > kLdsBudget ? 0 : lpb;
+  constexpr int unit = TPL >= 64 ? 1 : 64 / TPL;
+  constexpr int BT = block_threads<N, THREADS>();
+  int lpb = TPL >= BT ? 1 : BT / TPL;
+  const size_t per_line = size_t(lds_line) * sizeof(cx<xch_t<T>>);
+  while (lpb > unit && lpb * per_line > kLdsBudget) --lpb;
+  lpb -= lpb % unit;
+  *lds_bytes = size_t(lpb) * per_line;
+  return (lpb == 0 || *lds_bytes > kLdsBudget) ? 0 : lpb;
 }
 
 template <typename T, int N>
@@ -551,10 +600,10 @@ static sofft_status propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, 
   PassArgs<T> ca = axis_args<T>(p, 1, psi, dt);
   ra.f_mid = ca.f_mid = f_mid;
   const int nx = int(p.ax[0].n), ny = int(p.ax[1].n);
-  const cx<T>* kxf = tab<T>(p.ax[0].kin_full64, p.ax[0].kin_full32);
-  const cx<T>* kxh = tab<T>(p.ax[0].kin_half64, p.ax[0].kin_half32);
-  const cx<T>* kyf = tab<T>(p.ax[1].kin_full64, p.ax[1].kin_full32);
-  const cx<T>* kyh = tab<T>(p.ax[1].kin_half64, p.ax[1].kin_half32);
+  const cx<double>* kxf = static_cast<const cx<double>*>(p.ax[0].kin_full64.p);
+  const cx<double>* kxh = static_cast<const cx<double>*>(p.ax[0].kin_half64.p);
+  const cx<double>* kyf = static_cast<const cx<double>*>(p.ax[1].kin_full64.p);
+  const cx<double>* kyh = static_cast<const cx<double>*>(p.ax[1].kin_half64.p);
   sofft_status st;
   // opening K_y/2
   ca.do_pot = 0;
@@ -577,7 +626,7 @@ static sofft_status propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, 
 template <typename T, int N>
 static sofft_status tdse1d(Plan& p, const PassArgs<T>& a, int64_t nsteps, hipStream_t s) {
   constexpr int TPL = N / Shape<N>::P;
-  const size_t lds = size_t(N + a.lds_line) * sizeof(cx<T>);
+  const size_t lds = size_t(N) * sizeof(cx<double>) + size_t(a.lds_line) * sizeof(cx<xch_t<T>>);
   if (lds > kLdsBudget) {
     set_error("ECS strip too long for the LDS budget");
     return SOFFT_EUNSUPPORTED;
@@ -586,8 +635,8 @@ static sofft_status tdse1d(Plan& p, const PassArgs<T>& a, int64_t nsteps, hipStr
   if (st != SOFFT_OK) return st;
   const Axis& A = p.ax[0];
   if ((st = p.timing.begin(SOFFT_KERNEL_1D, s)) != SOFFT_OK) return st;
-  k_tdse1d<T, N><<<1, TPL, lds, s>>>(a, tab<T>(A.kin_half64, A.kin_half32), tab<T>(A.kin_full64, A.kin_full32),
-                                    nsteps);
+  k_tdse1d<T, N><<<1, TPL, lds, s>>>(a, static_cast<const cx<double>*>(A.kin_half64.p),
+                                    static_cast<const cx<double>*>(A.kin_full64.p), nsteps);
   SOFFT_HIP_TRY(hipGetLastError());
   return p.timing.end(s);
 }

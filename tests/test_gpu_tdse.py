@@ -167,3 +167,46 @@ def test_norm2_and_zero_steps():
     torch.cuda.synchronize()
     assert np.array_equal(psi.cpu().numpy(), a)
     plan.close()
+
+
+# ---------------------------------------------------------------- FP32 mode
+# complex64 state in HBM, FP64 arithmetic and tables on chip (the state is
+# rounded to FP32 once per pass).  Error against the FP64 oracle, stated per
+# result; the FP32 target is 1e-5 relative L2.
+TOL32 = 1e-5
+
+
+@pytest.mark.parametrize("n,steps", [(128, 2000), (256, 500)])
+def test_fp32_2d_error_against_fp64_oracle(n, steps):
+    from paper_1505_06707_amd import sofft
+    print(f"2D c64 {n}^2 x {steps}", flush=True)
+    h = 0.2
+    L = n * h
+    R0 = 0.8 * L / 2
+    ax = ot.Axis(n, L, R0=R0)
+    psi0 = wl.gaussian_2d(ax.x, ax.x, **wl.packet_params(seed=n))
+    f = wl.Pulse().at_midpoints(0.0, 0.05, steps)
+    args = (n, n, L, L, R0, R0, 0.5, "secs", 1.0, 0.64, psi0, 0.05, f)
+    g = run_gpu_2d(*args, dtype=sofft.C64)
+    o = oracle_2d(*args)
+    err = rel_l2(g, o)
+    print(f"   rel L2 (c64 vs FP64 oracle) = {err:.3e}", flush=True)
+    assert err < TOL32
+
+
+def test_fp32_1d_error_against_fp64_oracle():
+    from paper_1505_06707_amd import sofft
+    c = wl.TDSE_1D
+    x = ot.Axis(c.n, c.L, R0=c.R0).x
+    psi0 = wl.gaussian_1d(x)
+    f = c.pulse.at_midpoints(0.0, c.dt, c.nsteps)
+    plan = sofft.Plan(c.n, c.L, R0=c.R0, theta=c.theta, charge=c.charge, a2=c.a2, dtype=sofft.C64)
+    psi = _dev(psi0.astype(np.complex64))
+    plan.propagate(psi, c.dt, c.nsteps, _dev(f))
+    torch.cuda.synchronize()
+    g = psi.cpu().numpy().astype(np.complex128)
+    plan.close()
+    o = oracle_1d(c.n, c.L, c.R0, c.theta, "secs", c.charge, c.a2, psi0, c.dt, f)
+    err = rel_l2(g, o)
+    print(f"   1D c64 4096 x 4000: rel L2 = {err:.3e}", flush=True)
+    assert err < TOL32
