@@ -147,6 +147,52 @@ sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_ener
 sofft_status sofft_sse_apply(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double field,
                              void* stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent 2D propagations of uneven size advanced together (the
+ * step of Sec. II, as in sofft_propagate, applied to every run).  Runs with an
+ * identical problem statement share one set of tables and are processed by
+ * the same launches: one pass covers the lines of all of them.  Launch shapes
+ * (threads per block; one block per tile of lines or a persistent grid of the
+ * resident blocks) are chosen per shape on the first propagation by timing
+ * the candidates on scratch states the batch allocates and frees.  Steady
+ * steps are replayed from a captured HIP graph (one branch per shape). */
+typedef struct sofft_batch sofft_batch;
+
+/* nrun problems (host array), all 2D and of one dtype; each must be valid for
+ * sofft_plan_create.  The batch owns the tables of its distinct shapes, two
+ * device pointer tables per shape, one stream and event per shape. */
+sofft_status sofft_batch_create(const sofft_problem* probs, int32_t nrun, sofft_batch** out);
+
+/* Free the batch (after the work using it has finished). */
+sofft_status sofft_batch_destroy(sofft_batch* b);
+
+/* Advance every run by nsteps steps of length dt.
+ *   psi      host array of nrun device pointers; run r holds n_x n_y elements
+ *            of its problem (layout and element type as in sofft_propagate)
+ *   f_mid    device, [nrun][nsteps] doubles: f of run r at the midpoint of
+ *            step s is f_mid[r * nsteps + s]; NULL when no run has a field
+ *   norm2    host, nrun doubles: ||psi_r||^2 after the steps, accumulated in
+ *            FP64 (NULL: not computed; when given the call blocks)
+ * The call waits for the stream once, to upload the pointer tables; the steps
+ * are otherwise asynchronous.  The first call with nsteps > 0 times the launch
+ * shapes (a few passes per shape on scratch memory of the size of that
+ * shape's runs).  Calls on one batch must not overlap. */
+sofft_status sofft_batch_propagate(sofft_batch* b, void* const* psi, double dt, int64_t nsteps,
+                                   const double* f_mid, double* norm2, void* stream);
+
+/* Steady steps per captured graph replay (default 32; 0 = plain launches). */
+sofft_status sofft_batch_set_graph_steps(sofft_batch* b, int32_t steps);
+
+/* Launch shape of the row (pass 0) or column (pass 1) launches of the shape
+ * that run belongs to: threads per block (256, 512 or 1024; the kernels clamp
+ * it to what a line needs and the LDS holds) and grid (0 = one block per tile
+ * of lines, else at most that many blocks loop over the tiles).  Setting a
+ * shape marks it as tuned (no timing); reading returns zeros before tuning. */
+sofft_status sofft_batch_set_launch_shape(sofft_batch* b, int32_t run, int32_t pass, int32_t threads,
+                                          int32_t grid);
+sofft_status sofft_batch_launch_shape(const sofft_batch* b, int32_t run, int32_t pass, int32_t* threads,
+                                      int32_t* grid);
+
 /* Kernels whose launches can be timed (see sofft_timing_*). */
 typedef enum {
   SOFFT_KERNEL_ROW = 0,   /* 2D row pass (x lines) of the propagation */

@@ -88,12 +88,45 @@ void free_axis(Axis& a);
 sofft_status dev_upload(DevBuf& b, const void* host, size_t bytes);
 void dev_free(DevBuf& b);
 
+// Launch shape of a 2D pass: threads per block (0 = default) and grid (0 =
+// one block per tile of lines, else a persistent grid of at most that many
+// blocks looping over the tiles).
+struct PassLaunch {
+  int threads = 0;
+  int grid = 0;
+};
+
+// One row or column pass over the states of nruns runs that share a plan
+// (batched propagation).  runs / f_runs are device arrays of nruns pointers;
+// the field of run r at step s is f_runs[r][s + *step_base] (f_runs may be
+// null: no field; step_base may be null: offset 0).
+struct PassRequest {
+  bool row = true;
+  bool half_kinetic = false;
+  int do_pot = 1;
+  double dt = 0;
+  void* const* runs = nullptr;
+  const double* const* f_runs = nullptr;
+  int nruns = 0;
+  int64_t step = 0;
+  const int64_t* step_base = nullptr;
+  PassLaunch cfg;
+  Timing* timing = nullptr;
+};
+
 // Launchers (tdse.hip).
 sofft_status launch_propagate_1d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
                                  hipStream_t s);
 sofft_status launch_propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
                                  hipStream_t s);
 sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s);
+sofft_status launch_pass(Plan& p, const PassRequest& rq, hipStream_t s);
+sofft_status pass_residency(const Plan& p, bool row, int threads, int* blocks_per_cu, int* block_threads);
+// *counter += delta by one device thread (graph-safe step offsets).
+sofft_status launch_step_add(int64_t* counter, int64_t delta, bool set, hipStream_t s);
+// partials[r * 64 + b] = partial sums of |psi_r|^2 (64 blocks per run), FP64.
+sofft_status launch_norm2_runs(const void* const* runs_dev, int nruns, int64_t npoints, bool c128,
+                               double* partials, hipStream_t s);
 bool supported_length(int64_t n);
 
 // Stationary solver (sse.hip).

@@ -199,6 +199,8 @@ sofft_status upload_static(Axis& a) {
 // prepared for parallel cyclic reduction.
 sofft_status ensure_dt(Axis& a, double dt) {
   if (a.have_dt && a.dt == dt) return SOFFT_OK;
+  // Work already enqueued may still read the tables of the previous dt.
+  if (a.have_dt) SOFFT_HIP_TRY(hipDeviceSynchronize());
   const int64_t n = a.n;
   std::vector<zc> kf(n), kh(n);
   for (int64_t j = 0; j < n; ++j) {
@@ -274,6 +276,10 @@ void free_axis(Axis& a) {
 using namespace sofft;
 
 struct sofft_plan : public Plan {};
+
+namespace sofft {
+Plan& plan_of(sofft_plan* p) { return *p; }
+}  // namespace sofft
 
 extern "C" {
 

@@ -36,12 +36,17 @@ using xch_t = typename Xch<T>::type;
 
 template <typename T>
 struct PassArgs {
-  cx<T>* psi;
+  cx<T>* psi;              // the state (one run), or
+  cx<T>* const* runs;      // device array of nruns states of the same shape
+  const double* const* f_runs;   // device array of their f_mid rows (may be null)
+  int nruns;               // runs of this shape (lines of a pass: nruns * ny or nruns * nx)
+  int ntiles;              // blocks of lines over all runs
+  const int64_t* step_base;      // device offset added to step (graph replays), or null
   int nx, ny;
   const cx<double>* tw;    // twiddles exp(-2 pi i u/n) of the pass axis
   const cx<double>* kin;   // kinetic phase (with 1/n) of the pass axis
   int do_pot;         // apply the potential half-step and the CN sweep
-  const double* f_mid;
+  const double* f_mid;     // f_mid of the single state
   int64_t step;
   double ht;          // dt/2
   double charge, a2;
@@ -241,6 +246,22 @@ __device__ __forceinline__ void cn_block(int lpb, const PassArgs<T>& a, LineOf l
   __syncthreads();
 }
 
+template <typename T>
+__device__ __forceinline__ cx<T>* run_state(const PassArgs<T>& a, int run) {
+  return a.runs ? a.runs[run] : a.psi;
+}
+template <typename T>
+__device__ __forceinline__ const double* run_field(const PassArgs<T>& a, int run) {
+  return a.runs ? (a.f_runs ? a.f_runs[run] : nullptr) : a.f_mid;
+}
+template <typename T>
+__device__ __forceinline__ int64_t pass_step(const PassArgs<T>& a) {
+  return a.step + (a.step_base ? *a.step_base : 0);
+}
+
+// The lines of a pass (rows or columns of every run, run-major) are cut into
+// tiles of blockDim.x / TPL lines; block b takes tiles b, b + gridDim.x, ...
+// (one tile per block, or a persistent grid sized to the resident blocks).
 // Block LDS layout of the 2D passes: [line 0][line 1]...; a block holds
 // blockDim.x / TPL lines of a.lds_line elements.  FFT twiddles and CN
 // coefficients are read from global memory (they stay in the vector L1).
@@ -253,79 +274,88 @@ __global__ void __launch_bounds__((block_threads<N, kRowThreads>()), min_waves_p
   cx<X>* lines = reinterpret_cast<cx<X>*>(smem);
   const int lpb = blockDim.x / TPL;
   const int l = threadIdx.x / TPL, t = threadIdx.x - l * TPL;
-  const int row = blockIdx.x * lpb + l;
-  const bool live = row < a.ny;
-  const int crow = live ? row : 0;
   const LineLDS<X> L{lines, l * a.lds_line, 1};
-  cx<T>* line = a.psi + size_t(crow) * N;
+  const int nlines = a.nruns * a.ny;
   const bool cn = a.do_pot && a.m > 0;
-  cx<double> v[P];
+  const int64_t step = pass_step(a);
   cx<double> kin[P];
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = live ? widen(line[t + TPL * s]) : cx<double>{0.0, 0.0};
-#pragma unroll
   for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
-  // inputs of the potential, fetched before the transforms
+  // inputs of the potential that do not depend on the row
   cx<double> zxs[P];
   double xs[P];
-  double f = 0.0;
-  cx<double> zy{0.0, 0.0};
   if (a.do_pot) {
 #pragma unroll
     for (int s = 0; s < P; ++s) {
       zxs[s] = a.zx[t + TPL * s];
       xs[s] = a.x[t + TPL * s];
     }
-    f = a.f_mid ? a.f_mid[a.step] : 0.0;
-    if (a.zy) zy = a.zy[crow];
   }
-  fft<X, N, -1>(v, L, t, a.tw);
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const int g = tile * lpb + l;
+    const bool live = g < nlines;
+    const int gg = live ? g : 0;
+    const int run = gg / a.ny, crow = gg - run * a.ny;
+    cx<T>* line = run_state(a, run) + size_t(crow) * N;
+    cx<double> v[P];
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
-  fft<X, N, +1>(v, L, t, a.tw);
-  if (a.do_pot) {
-    // Rows outside the y-strip get both potential half-steps here (C_y is the
-    // identity on them); rows on it get the first, the column pass the second.
-    // On the x-strip the phase waits in LDS (from 2m) across the CN, or is
-    // evaluated again after it when LDS holds FP32.
-    const cx<double> zy2a = cmul(zy, zy) + cx<double>{a.a2, 0.0};
-    const bool both = strip_pos_rt(crow, a.j0y, a.ny) >= a.my;
-    const int m = a.m;
-#pragma unroll
-    for (int s = 0; s < P; ++s) {
-      const cx<double> ph = potential_phase(cmul(zxs[s], zxs[s]) + zy2a, a.charge, f * xs[s], a.ht);
-      const int p = strip_pos<N>(t + TPL * s, a.j0);
-      if (p < m) {
-        v[s] = cmul(v[s], ph);
-        L[p] = narrow<X>(v[s]);
-        if constexpr (park) {
-          if (both) L[2 * m + p] = ph;
-        }
-      } else {
-        v[s] = cmul(v[s], both ? cmul(ph, ph) : ph);
-      }
+    for (int s = 0; s < P; ++s) v[s] = live ? widen(line[t + TPL * s]) : cx<double>{0.0, 0.0};
+    double f = 0.0;
+    cx<double> zy{0.0, 0.0};
+    if (a.do_pot) {
+      const double* fm = run_field(a, run);
+      f = fm ? fm[step] : 0.0;
+      if (a.zy) zy = a.zy[crow];
     }
-    if (cn) {
-      cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln * a.lds_line, 1}; });
+    fft<X, N, -1>(v, L, t, a.tw);
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
+    fft<X, N, +1>(v, L, t, a.tw);
+    if (a.do_pot) {
+      // Rows outside the y-strip get both potential half-steps here (C_y is the
+      // identity on them); rows on it get the first, the column pass the second.
+      // On the x-strip the phase waits in LDS (from 2m) across the CN, or is
+      // evaluated again after it when LDS holds FP32.
+      const cx<double> zy2a = cmul(zy, zy) + cx<double>{a.a2, 0.0};
+      const bool both = strip_pos_rt(crow, a.j0y, a.ny) >= a.my;
+      const int m = a.m;
 #pragma unroll
       for (int s = 0; s < P; ++s) {
+        const cx<double> ph = potential_phase(cmul(zxs[s], zxs[s]) + zy2a, a.charge, f * xs[s], a.ht);
         const int p = strip_pos<N>(t + TPL * s, a.j0);
         if (p < m) {
-          v[s] = 2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s];
-          if (both) {
-            if constexpr (park) {
-              v[s] = cmul(v[s], widen(L[2 * m + p]));
-            } else {
-              v[s] = cmul(v[s], potential_phase(cmul(zxs[s], zxs[s]) + zy2a, a.charge, f * xs[s], a.ht));
+          v[s] = cmul(v[s], ph);
+          L[p] = narrow<X>(v[s]);
+          if constexpr (park) {
+            if (both) L[2 * m + p] = ph;
+          }
+        } else {
+          v[s] = cmul(v[s], both ? cmul(ph, ph) : ph);
+        }
+      }
+      if (cn) {
+        cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln * a.lds_line, 1}; });
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+          const int p = strip_pos<N>(t + TPL * s, a.j0);
+          if (p < m) {
+            v[s] = 2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s];
+            if (both) {
+              if constexpr (park) {
+                v[s] = cmul(v[s], widen(L[2 * m + p]));
+              } else {
+                v[s] = cmul(v[s], potential_phase(cmul(zxs[s], zxs[s]) + zy2a, a.charge, f * xs[s], a.ht));
+              }
             }
           }
         }
       }
     }
-  }
-  if (live) {
+    if (live) {
 #pragma unroll
-    for (int s = 0; s < P; ++s) line[t + TPL * s] = narrow<T>(v[s]);
+      for (int s = 0; s < P; ++s) line[t + TPL * s] = narrow<T>(v[s]);
+    }
+    __syncthreads();   // LDS is reused by the next tile
   }
 }
 
@@ -345,51 +375,58 @@ __global__ void __launch_bounds__((block_threads<N, kColThreads>()), min_waves_p
   cx<X>* lines = reinterpret_cast<cx<X>*>(smem);
   const int lpb = blockDim.x / TPL;
   const int c = threadIdx.x % lpb, t = threadIdx.x / lpb;
-  const int col = xcd_block(blockIdx.x, gridDim.x) * lpb + c;
-  const bool live = col < a.nx;
-  const int ccol = live ? col : 0;
   const LineLDS<X> L{lines, c, lpb};
-  cx<T>* base = a.psi + ccol;
   const size_t ld = size_t(a.nx);
+  const int nlines = a.nruns * a.nx;
   const bool cn = a.do_pot && a.m > 0;
-  cx<double> v[P];
+  const int64_t step = pass_step(a);
   cx<double> kin[P];
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = live ? widen(base[size_t(t + TPL * s) * ld]) : cx<double>{0.0, 0.0};
-#pragma unroll
   for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
-  if (cn) {
-    // C_y and the second potential half-step, on the y-strip only.
-    const double f = a.f_mid ? a.f_mid[a.step] : 0.0;
-    const cx<double> zx = a.zx[ccol];
-    const double fx = f * a.x[ccol];
-    const int m = a.m;
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const int g = xcd_block(tile, a.ntiles) * lpb + c;
+    const bool live = g < nlines;
+    const int gg = live ? g : 0;
+    const int run = gg / a.nx, ccol = gg - run * a.nx;
+    cx<T>* base = run_state(a, run) + ccol;
+    cx<double> v[P];
 #pragma unroll
-    for (int s = 0; s < P; ++s) {
-      const int p = strip_pos<N>(t + TPL * s, a.j0);
-      if (p < m) L[p] = narrow<X>(v[s]);
-    }
-    cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln, lpb}; });
-    const cx<double> zx2a = cmul(zx, zx) + cx<double>{a.a2, 0.0};
+    for (int s = 0; s < P; ++s) v[s] = live ? widen(base[size_t(t + TPL * s) * ld]) : cx<double>{0.0, 0.0};
+    if (cn) {
+      // C_y and the second potential half-step, on the y-strip only.
+      const double* fm = run_field(a, run);
+      const double f = fm ? fm[step] : 0.0;
+      const cx<double> zx = a.zx[ccol];
+      const double fx = f * a.x[ccol];
+      const int m = a.m;
 #pragma unroll
-    for (int s = 0; s < P; ++s) {
-      const int e = t + TPL * s;
-      const int p = strip_pos<N>(e, a.j0);
-      if (p < m) {
-        const cx<double> zy = a.zy[e];
-        v[s] = cmul(2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s],
-                    potential_phase(zx2a + cmul(zy, zy), a.charge, fx, a.ht));
+      for (int s = 0; s < P; ++s) {
+        const int p = strip_pos<N>(t + TPL * s, a.j0);
+        if (p < m) L[p] = narrow<X>(v[s]);
       }
+      cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln, lpb}; });
+      const cx<double> zx2a = cmul(zx, zx) + cx<double>{a.a2, 0.0};
+#pragma unroll
+      for (int s = 0; s < P; ++s) {
+        const int e = t + TPL * s;
+        const int p = strip_pos<N>(e, a.j0);
+        if (p < m) {
+          const cx<double> zy = a.zy[e];
+          v[s] = cmul(2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s],
+                      potential_phase(zx2a + cmul(zy, zy), a.charge, fx, a.ht));
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  fft<X, N, -1>(v, L, t, a.tw);
+    fft<X, N, -1>(v, L, t, a.tw);
 #pragma unroll
-  for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
-  fft<X, N, +1>(v, L, t, a.tw);
-  if (live) {
+    for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
+    fft<X, N, +1>(v, L, t, a.tw);
+    if (live) {
 #pragma unroll
-    for (int s = 0; s < P; ++s) base[size_t(t + TPL * s) * ld] = narrow<T>(v[s]);
+      for (int s = 0; s < P; ++s) base[size_t(t + TPL * s) * ld] = narrow<T>(v[s]);
+    }
+    __syncthreads();   // LDS is reused by the next tile
   }
 }
 
@@ -433,6 +470,29 @@ __global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const
   for (int s = 0; s < P; ++s) a.psi[t + TPL * s] = narrow<T>(v[s]);
 }
 
+__global__ void k_step_add(int64_t* counter, int64_t delta, int set) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = set ? delta : *counter + delta;
+}
+
+// Per-run FP64 partial sums of |psi|^2: block (b, r) of a 64 x nruns grid.
+template <typename T>
+__global__ void __launch_bounds__(256) k_norm2_runs(const cx<T>* const* runs, int64_t n, double* partials) {
+  __shared__ double red[256];
+  const cx<T>* psi = runs[blockIdx.y];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const cx<T> v = psi[i];
+    acc += double(v.re) * double(v.re) + double(v.im) * double(v.im);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[size_t(blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_norm2(const cx<T>* psi, int64_t n, double* partials) {
   __shared__ double red[256];
@@ -471,6 +531,7 @@ static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   Axis& A = p.ax[axis];
   PassArgs<T> a{};
   a.psi = static_cast<cx<T>*>(psi);
+  a.nruns = 1;
   a.nx = int(p.ax[0].n);
   a.ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
   a.tw = static_cast<const cx<double>*>(A.tw64.p);
@@ -526,16 +587,15 @@ static sofft_status set_lds(K kernel, size_t bytes) {
     default: break;                               \
   }
 
-// Lines per block of a 2D pass: THREADS threads' worth (at least one line),
-// fewer when the lines' LDS would exceed the budget.
-// Blocks are whole wavefronts (the CN gives each wavefront whole lines), so
-// with lines shorter than a wavefront lpb is a multiple of 64/TPL.
-template <typename T, int N, int THREADS>
-static int lines_per_block(int lds_line, size_t* lds_bytes) {
+// Lines per block of a 2D pass with `threads` threads (at least one line),
+// fewer when the lines' LDS would exceed the budget.  Blocks are whole
+// wavefronts (the CN gives each wavefront whole lines), so with lines shorter
+// than a wavefront lpb is a multiple of 64/TPL.
+template <typename T, int N>
+static int lines_per_block(int threads, int lds_line, size_t* lds_bytes) {
   constexpr int TPL = N / Shape<N>::P;
   constexpr int unit = TPL >= 64 ? 1 : 64 / TPL;
-  constexpr int BT = block_threads<N, THREADS>();
-  int lpb = TPL >= BT ? 1 : BT / TPL;
+  int lpb = TPL >= threads ? 1 : threads / TPL;
   const size_t per_line = size_t(lds_line) * sizeof(cx<xch_t<T>>);
   while (lpb > unit && lpb * per_line > kLdsBudget) --lpb;
   lpb -= lpb % unit;
@@ -543,53 +603,97 @@ static int lines_per_block(int lds_line, size_t* lds_bytes) {
   return (lpb == 0 || *lds_bytes > kLdsBudget) ? 0 : lpb;
 }
 
-template <typename T, int N>
-static sofft_status row_pass(const PassArgs<T>& a, hipStream_t s, Timing& tm) {
-  constexpr int TPL = N / Shape<N>::P;
-  size_t lds = 0;
-  const int lpb = lines_per_block<T, N, kRowThreads>(a.lds_line, &lds);
-  if (lpb == 0) {
-    set_error("ECS strip too long for the LDS budget");
-    return SOFFT_EUNSUPPORTED;
-  }
-  sofft_status st = set_lds(k_row_pass<T, N>, lds);
-  if (st != SOFFT_OK) return st;
-  const int blocks = (a.ny + lpb - 1) / lpb;
-  if ((st = tm.begin(SOFFT_KERNEL_ROW, s)) != SOFFT_OK) return st;
-  k_row_pass<T, N><<<blocks, lpb * TPL, lds, s>>>(a);
-  SOFFT_HIP_TRY(hipGetLastError());
-  return tm.end(s);
+template <typename T, int N, bool ROW>
+static void* pass_kernel() {
+  return ROW ? reinterpret_cast<void*>(k_row_pass<T, N>) : reinterpret_cast<void*>(k_col_pass<T, N>);
 }
 
-template <typename T, int N>
-static sofft_status col_pass(const PassArgs<T>& a, hipStream_t s, Timing& tm) {
+// One pass over the lines of every run in a (row pass if ROW, else column
+// pass).  cfg.threads = 0 takes the default block size; cfg.grid = 0 launches
+// one block per tile, otherwise at most cfg.grid blocks loop over the tiles.
+template <typename T, int N, bool ROW>
+static sofft_status pass(PassArgs<T> a, PassLaunch cfg, hipStream_t s, Timing* tm) {
   constexpr int TPL = N / Shape<N>::P;
+  constexpr int maxt = block_threads<N, ROW ? kRowThreads : kColThreads>();
+  const int threads = cfg.threads > 0 ? std::min(cfg.threads, maxt) : maxt;
   size_t lds = 0;
-  const int lpb = lines_per_block<T, N, kColThreads>(a.lds_line, &lds);
+  const int lpb = lines_per_block<T, N>(threads, a.lds_line, &lds);
   if (lpb == 0) {
     set_error("ECS strip too long for the LDS budget");
     return SOFFT_EUNSUPPORTED;
   }
-  sofft_status st = set_lds(k_col_pass<T, N>, lds);
+  sofft_status st = ROW ? set_lds(k_row_pass<T, N>, lds) : set_lds(k_col_pass<T, N>, lds);
   if (st != SOFFT_OK) return st;
-  const int blocks = (a.nx + lpb - 1) / lpb;
-  if ((st = tm.begin(SOFFT_KERNEL_COL, s)) != SOFFT_OK) return st;
-  k_col_pass<T, N><<<blocks, lpb * TPL, lds, s>>>(a);
+  const int lines = a.nruns * (ROW ? a.ny : a.nx);
+  a.ntiles = (lines + lpb - 1) / lpb;
+  const int blocks = cfg.grid > 0 ? std::min(cfg.grid, a.ntiles) : a.ntiles;
+  if (tm && (st = tm->begin(ROW ? SOFFT_KERNEL_ROW : SOFFT_KERNEL_COL, s)) != SOFFT_OK) return st;
+  if (ROW)
+    k_row_pass<T, N><<<blocks, lpb * TPL, lds, s>>>(a);
+  else
+    k_col_pass<T, N><<<blocks, lpb * TPL, lds, s>>>(a);
   SOFFT_HIP_TRY(hipGetLastError());
-  return tm.end(s);
+  return tm ? tm->end(s) : SOFFT_OK;
 }
+
+// Resident blocks per CU of a pass kernel at a block size (for persistent grids).
+template <typename T, int N, bool ROW>
+static sofft_status pass_occupancy(int lds_line, int threads, int* blocks_per_cu, int* block_threads_out) {
+  constexpr int TPL = N / Shape<N>::P;
+  constexpr int maxt = block_threads<N, ROW ? kRowThreads : kColThreads>();
+  threads = threads > 0 ? std::min(threads, maxt) : maxt;
+  size_t lds = 0;
+  const int lpb = lines_per_block<T, N>(threads, lds_line, &lds);
+  if (lpb == 0) {
+    set_error("ECS strip too long for the LDS budget");
+    return SOFFT_EUNSUPPORTED;
+  }
+  sofft_status st = ROW ? set_lds(k_row_pass<T, N>, lds) : set_lds(k_col_pass<T, N>, lds);
+  if (st != SOFFT_OK) return st;
+  int nb = 0;
+  SOFFT_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pass_kernel<T, N, ROW>(), lpb * TPL, lds));
+  *blocks_per_cu = nb;
+  *block_threads_out = lpb * TPL;
+  return SOFFT_OK;
+}
+
+#define SOFFT_PASS_SWITCH(n, EXPR_N)                                                  \
+  switch (n) {                                                                        \
+    case 16: { constexpr int N_ = 16; return EXPR_N; }                                \
+    case 32: { constexpr int N_ = 32; return EXPR_N; }                                \
+    case 48: { constexpr int N_ = 48; return EXPR_N; }                                \
+    case 64: { constexpr int N_ = 64; return EXPR_N; }                                \
+    case 96: { constexpr int N_ = 96; return EXPR_N; }                                \
+    case 128: { constexpr int N_ = 128; return EXPR_N; }                              \
+    case 192: { constexpr int N_ = 192; return EXPR_N; }                              \
+    case 256: { constexpr int N_ = 256; return EXPR_N; }                              \
+    case 384: { constexpr int N_ = 384; return EXPR_N; }                              \
+    case 512: { constexpr int N_ = 512; return EXPR_N; }                              \
+    case 768: { constexpr int N_ = 768; return EXPR_N; }                              \
+    case 1024: { constexpr int N_ = 1024; return EXPR_N; }                            \
+    default: break;                                                                   \
+  }
 
 template <typename T>
-static sofft_status row_pass_n(int n, const PassArgs<T>& a, hipStream_t s, Timing& tm) {
-  SOFFT_LENGTH_SWITCH(n, row_pass, T, a, s, tm)
-  set_error("unsupported row length");
+static sofft_status pass_n(bool row, const PassArgs<T>& a, PassLaunch cfg, hipStream_t s, Timing* tm) {
+  const int n = row ? a.nx : a.ny;
+  if (row) {
+    SOFFT_PASS_SWITCH(n, (pass<T, N_, true>(a, cfg, s, tm)))
+  } else {
+    SOFFT_PASS_SWITCH(n, (pass<T, N_, false>(a, cfg, s, tm)))
+  }
+  set_error("unsupported 2D line length");
   return SOFFT_EUNSUPPORTED;
 }
 
 template <typename T>
-static sofft_status col_pass_n(int n, const PassArgs<T>& a, hipStream_t s, Timing& tm) {
-  SOFFT_LENGTH_SWITCH(n, col_pass, T, a, s, tm)
-  set_error("unsupported column length");
+static sofft_status occupancy_n(bool row, int n, int lds_line, int threads, int* nb, int* bt) {
+  if (row) {
+    SOFFT_PASS_SWITCH(n, (pass_occupancy<T, N_, true>(lds_line, threads, nb, bt)))
+  } else {
+    SOFFT_PASS_SWITCH(n, (pass_occupancy<T, N_, false>(lds_line, threads, nb, bt)))
+  }
+  set_error("unsupported 2D line length");
   return SOFFT_EUNSUPPORTED;
 }
 
@@ -599,28 +703,61 @@ static sofft_status propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, 
   PassArgs<T> ra = axis_args<T>(p, 0, psi, dt);
   PassArgs<T> ca = axis_args<T>(p, 1, psi, dt);
   ra.f_mid = ca.f_mid = f_mid;
-  const int nx = int(p.ax[0].n), ny = int(p.ax[1].n);
   const cx<double>* kxf = static_cast<const cx<double>*>(p.ax[0].kin_full64.p);
   const cx<double>* kxh = static_cast<const cx<double>*>(p.ax[0].kin_half64.p);
   const cx<double>* kyf = static_cast<const cx<double>*>(p.ax[1].kin_full64.p);
   const cx<double>* kyh = static_cast<const cx<double>*>(p.ax[1].kin_half64.p);
+  const PassLaunch dflt{};
   sofft_status st;
   // opening K_y/2
   ca.do_pot = 0;
   ca.kin = kyh;
-  if ((st = col_pass_n<T>(ny, ca, s, p.timing)) != SOFFT_OK) return st;
+  if ((st = pass_n<T>(false, ca, dflt, s, &p.timing)) != SOFFT_OK) return st;
   ra.do_pot = ca.do_pot = 1;
   for (int64_t n = 0; n < nsteps; ++n) {
     ra.step = ca.step = n;
     ra.kin = n == 0 ? kxh : kxf;
     ca.kin = n + 1 == nsteps ? kyh : kyf;
-    if ((st = row_pass_n<T>(nx, ra, s, p.timing)) != SOFFT_OK) return st;
-    if ((st = col_pass_n<T>(ny, ca, s, p.timing)) != SOFFT_OK) return st;
+    if ((st = pass_n<T>(true, ra, dflt, s, &p.timing)) != SOFFT_OK) return st;
+    if ((st = pass_n<T>(false, ca, dflt, s, &p.timing)) != SOFFT_OK) return st;
   }
   // closing K_x/2
   ra.do_pot = 0;
   ra.kin = kxh;
-  return row_pass_n<T>(nx, ra, s, p.timing);
+  return pass_n<T>(true, ra, dflt, s, &p.timing);
+}
+
+sofft_status launch_pass(Plan& p, const PassRequest& rq, hipStream_t s) {
+  const int axis = rq.row ? 0 : 1;
+  const Axis& A = p.ax[axis];
+  const cx<double>* kin = static_cast<const cx<double>*>(rq.half_kinetic ? A.kin_half64.p : A.kin_full64.p);
+  if (p.prob.dtype == SOFFT_C128) {
+    PassArgs<double> a = axis_args<double>(p, axis, nullptr, rq.dt);
+    a.runs = reinterpret_cast<cx<double>* const*>(rq.runs);
+    a.f_runs = rq.f_runs;
+    a.nruns = rq.nruns;
+    a.step = rq.step;
+    a.step_base = rq.step_base;
+    a.do_pot = rq.do_pot;
+    a.kin = kin;
+    return pass_n<double>(rq.row, a, rq.cfg, s, rq.timing);
+  }
+  PassArgs<float> a = axis_args<float>(p, axis, nullptr, rq.dt);
+  a.runs = reinterpret_cast<cx<float>* const*>(rq.runs);
+  a.f_runs = rq.f_runs;
+  a.nruns = rq.nruns;
+  a.step = rq.step;
+  a.step_base = rq.step_base;
+  a.do_pot = rq.do_pot;
+  a.kin = kin;
+  return pass_n<float>(rq.row, a, rq.cfg, s, rq.timing);
+}
+
+sofft_status pass_residency(const Plan& p, bool row, int threads, int* blocks_per_cu, int* block_threads_out) {
+  const Axis& A = p.ax[row ? 0 : 1];
+  const int lds_line = int(std::max<int64_t>(lds_elems_for(A.n), 3 * A.m));
+  return p.prob.dtype == SOFFT_C128 ? occupancy_n<double>(row, int(A.n), lds_line, threads, blocks_per_cu, block_threads_out)
+                                    : occupancy_n<float>(row, int(A.n), lds_line, threads, blocks_per_cu, block_threads_out);
 }
 
 template <typename T, int N>
@@ -692,6 +829,23 @@ sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s) 
   double acc = 0.0;
   for (int b = 0; b < blocks; ++b) acc += p.host_partials[b];
   *out = acc;
+  return SOFFT_OK;
+}
+
+sofft_status launch_step_add(int64_t* counter, int64_t delta, bool set, hipStream_t s) {
+  k_step_add<<<1, 64, 0, s>>>(counter, delta, set ? 1 : 0);
+  SOFFT_HIP_TRY(hipGetLastError());
+  return SOFFT_OK;
+}
+
+sofft_status launch_norm2_runs(const void* const* runs_dev, int nruns, int64_t npoints, bool c128,
+                               double* partials, hipStream_t s) {
+  const dim3 grid(64, nruns);
+  if (c128)
+    k_norm2_runs<double><<<grid, 256, 0, s>>>(reinterpret_cast<const cx<double>* const*>(runs_dev), npoints, partials);
+  else
+    k_norm2_runs<float><<<grid, 256, 0, s>>>(reinterpret_cast<const cx<float>* const*>(runs_dev), npoints, partials);
+  SOFFT_HIP_TRY(hipGetLastError());
   return SOFFT_OK;
 }
 

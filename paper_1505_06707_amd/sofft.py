@@ -69,6 +69,15 @@ _SIGS = {
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_sse_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_void_p]),
+    "sofft_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "sofft_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sofft_batch_propagate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_batch_set_graph_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "sofft_batch_set_launch_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.c_int32, ctypes.c_int32]),
+    "sofft_batch_launch_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "sofft_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sofft_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
@@ -236,3 +245,85 @@ class Plan:
         out = ctypes.c_double()
         _check(lib().sofft_norm2(self._h, ptr, ctypes.byref(out), _stream(stream)))
         return out.value
+
+
+def problem(n, L, R0=None, theta=0.5, contour=SECS, charge=1.0, a2=2.0, dtype=C128):
+    """A sofft_problem structure (the arguments of Plan)."""
+    n = list(n) if isinstance(n, (list, tuple)) else [n]
+    L = list(L) if isinstance(L, (list, tuple)) else [L] * len(n)
+    if R0 is None:
+        R0 = [l / 2 * 0.8 for l in L]
+    R0 = list(R0) if isinstance(R0, (list, tuple)) else [R0] * len(n)
+    p = Problem()
+    p.ndim = len(n)
+    p.dtype = dtype
+    for d in range(len(n)):
+        p.n[d] = int(n[d])
+        p.L[d] = float(L[d])
+        p.R0[d] = float(R0[d])
+    p.theta = float(theta)
+    p.contour = int(contour)
+    p.charge = float(charge)
+    p.a2 = float(a2)
+    return p
+
+
+class Batch:
+    """Many 2D propagations of uneven size advanced together (sofft_batch_*).
+
+    problems: list of Problem structures (see problem()), all 2D, one dtype."""
+
+    def __init__(self, problems):
+        arr = (Problem * len(problems))(*problems)
+        h = ctypes.c_void_p()
+        _check(lib().sofft_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(problems), ctypes.byref(h)))
+        self._h = h
+        self.problems = list(problems)
+        self.dtype = problems[0].dtype
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sofft_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self, r):
+        p = self.problems[r]
+        return (int(p.n[1]), int(p.n[0]))
+
+    def propagate(self, states, dt, nsteps, f_mid=None, norms=True, stream=None):
+        """Advance every state (list of device tensors, in place); returns the
+        FP64 squared norms (numpy array) when norms is true.
+
+        f_mid: float64 device tensor [nrun][nsteps] or None."""
+        import torch
+        if len(states) != len(self.problems):
+            raise ValueError("one state per run is needed")
+        tdt = torch.complex128 if self.dtype == C128 else torch.complex64
+        ptrs = (ctypes.c_void_p * len(states))()
+        for r, t in enumerate(states):
+            ny, nx = self.shape(r)
+            ptrs[r] = _dev_ptr(t, tdt, ny * nx, f"state {r}").value
+        fptr = ctypes.c_void_p(0) if f_mid is None else _dev_ptr(f_mid, torch.float64, len(states) * nsteps, "f_mid")
+        out = np.zeros(len(states), dtype=np.float64)
+        optr = out.ctypes.data_as(ctypes.c_void_p) if norms else ctypes.c_void_p(0)
+        _check(lib().sofft_batch_propagate(self._h, ctypes.cast(ptrs, ctypes.c_void_p), float(dt), int(nsteps),
+                                           fptr, optr, _stream(stream)))
+        return out if norms else None
+
+    def set_graph_steps(self, steps):
+        _check(lib().sofft_batch_set_graph_steps(self._h, int(steps)))
+
+    def set_launch_shape(self, run, pass_, threads, grid):
+        _check(lib().sofft_batch_set_launch_shape(self._h, int(run), int(pass_), int(threads), int(grid)))
+
+    def launch_shape(self, run, pass_):
+        t = ctypes.c_int32()
+        g = ctypes.c_int32()
+        _check(lib().sofft_batch_launch_shape(self._h, int(run), int(pass_), ctypes.byref(t), ctypes.byref(g)))
+        return t.value, g.value
