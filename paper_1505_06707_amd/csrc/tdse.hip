@@ -178,6 +178,16 @@ constexpr int block_threads() {
   constexpr int cap = Shape<N>::P == 4 ? THREADS : (THREADS < 512 ? THREADS : 512);
   return N / Shape<N>::P > cap ? N / Shape<N>::P : cap;
 }
+// Persistent variants (a loop over tiles) hold more live registers: at most
+// 512 threads per block and two waves per SIMD, i.e. 256 VGPRs.
+template <int N, int THREADS, bool PERSIST>
+constexpr int kernel_threads() {
+  return PERSIST && block_threads<N, THREADS>() > 512 ? 512 : block_threads<N, THREADS>();
+}
+template <int N, bool PERSIST>
+constexpr int kernel_waves() {
+  return PERSIST ? 2 : min_waves_per_simd<N>();
+}
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -260,13 +270,28 @@ __device__ __forceinline__ int64_t pass_step(const PassArgs<T>& a) {
 }
 
 // The lines of a pass (rows or columns of every run, run-major) are cut into
-// tiles of blockDim.x / TPL lines; block b takes tiles b, b + gridDim.x, ...
-// (one tile per block, or a persistent grid sized to the resident blocks).
+// tiles of blockDim.x / TPL lines.  Without PERSIST block b takes tile b (the
+// grid has one block per tile); with it block b loops over tiles b,
+// b + gridDim.x, ... (a persistent grid sized to the resident blocks).  The
+// two are separate instantiations because the loop around the transforms
+// costs the one-tile kernels their register allocation (spills).
+template <bool PERSIST, typename Body>
+__device__ __forceinline__ void run_tiles(int ntiles, Body& body) {
+  if constexpr (PERSIST) {
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+      body(tile);
+      __syncthreads();   // LDS is reused by the next tile
+    }
+  } else {
+    body(blockIdx.x);
+  }
+}
+
 // Block LDS layout of the 2D passes: [line 0][line 1]...; a block holds
 // blockDim.x / TPL lines of a.lds_line elements.  FFT twiddles and CN
 // coefficients are read from global memory (they stay in the vector L1).
-template <typename T, int N>
-__global__ void __launch_bounds__((block_threads<N, kRowThreads>()), min_waves_per_simd<N>()) k_row_pass(PassArgs<T> a) {
+template <typename T, int N, bool PERSIST>
+__global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (kernel_waves<N, PERSIST>())) k_row_pass(PassArgs<T> a) {
   using X = xch_t<T>;
   constexpr bool park = std::is_same<X, double>::value;
   constexpr int P = Shape<N>::P, TPL = N / P;
@@ -278,20 +303,7 @@ __global__ void __launch_bounds__((block_threads<N, kRowThreads>()), min_waves_p
   const int nlines = a.nruns * a.ny;
   const bool cn = a.do_pot && a.m > 0;
   const int64_t step = pass_step(a);
-  cx<double> kin[P];
-#pragma unroll
-  for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
-  // inputs of the potential that do not depend on the row
-  cx<double> zxs[P];
-  double xs[P];
-  if (a.do_pot) {
-#pragma unroll
-    for (int s = 0; s < P; ++s) {
-      zxs[s] = a.zx[t + TPL * s];
-      xs[s] = a.x[t + TPL * s];
-    }
-  }
-  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+  auto body = [&](int tile) {
     const int g = tile * lpb + l;
     const bool live = g < nlines;
     const int gg = live ? g : 0;
@@ -300,6 +312,19 @@ __global__ void __launch_bounds__((block_threads<N, kRowThreads>()), min_waves_p
     cx<double> v[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = live ? widen(line[t + TPL * s]) : cx<double>{0.0, 0.0};
+    cx<double> kin[P];
+#pragma unroll
+    for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
+    // inputs of the potential, fetched before the transforms
+    cx<double> zxs[P];
+    double xs[P];
+    if (a.do_pot) {
+#pragma unroll
+      for (int s = 0; s < P; ++s) {
+        zxs[s] = a.zx[t + TPL * s];
+        xs[s] = a.x[t + TPL * s];
+      }
+    }
     double f = 0.0;
     cx<double> zy{0.0, 0.0};
     if (a.do_pot) {
@@ -355,8 +380,8 @@ __global__ void __launch_bounds__((block_threads<N, kRowThreads>()), min_waves_p
 #pragma unroll
       for (int s = 0; s < P; ++s) line[t + TPL * s] = narrow<T>(v[s]);
     }
-    __syncthreads();   // LDS is reused by the next tile
-  }
+  };
+  run_tiles<PERSIST>(a.ntiles, body);
 }
 
 // Column blocks are assigned so that the blocks one XCD runs hold adjacent
@@ -367,8 +392,8 @@ __device__ __forceinline__ int xcd_block(int b, int nblk) {
   return (b % 8) * (nblk / 8) + b / 8;
 }
 
-template <typename T, int N>
-__global__ void __launch_bounds__((block_threads<N, kColThreads>()), min_waves_per_simd<N>()) k_col_pass(PassArgs<T> a) {
+template <typename T, int N, bool PERSIST>
+__global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (kernel_waves<N, PERSIST>())) k_col_pass(PassArgs<T> a) {
   using X = xch_t<T>;
   constexpr int P = Shape<N>::P, TPL = N / P;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -380,10 +405,7 @@ __global__ void __launch_bounds__((block_threads<N, kColThreads>()), min_waves_p
   const int nlines = a.nruns * a.nx;
   const bool cn = a.do_pot && a.m > 0;
   const int64_t step = pass_step(a);
-  cx<double> kin[P];
-#pragma unroll
-  for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
-  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+  auto body = [&](int tile) {
     const int g = xcd_block(tile, a.ntiles) * lpb + c;
     const bool live = g < nlines;
     const int gg = live ? g : 0;
@@ -392,6 +414,9 @@ __global__ void __launch_bounds__((block_threads<N, kColThreads>()), min_waves_p
     cx<double> v[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = live ? widen(base[size_t(t + TPL * s) * ld]) : cx<double>{0.0, 0.0};
+    cx<double> kin[P];
+#pragma unroll
+    for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
     if (cn) {
       // C_y and the second potential half-step, on the y-strip only.
       const double* fm = run_field(a, run);
@@ -426,8 +451,8 @@ __global__ void __launch_bounds__((block_threads<N, kColThreads>()), min_waves_p
 #pragma unroll
       for (int s = 0; s < P; ++s) base[size_t(t + TPL * s) * ld] = narrow<T>(v[s]);
     }
-    __syncthreads();   // LDS is reused by the next tile
-  }
+  };
+  run_tiles<PERSIST>(a.ntiles, body);
 }
 
 // 1D: the whole propagation in one workgroup; psi stays in registers.
@@ -603,9 +628,16 @@ static int lines_per_block(int threads, int lds_line, size_t* lds_bytes) {
   return (lpb == 0 || *lds_bytes > kLdsBudget) ? 0 : lpb;
 }
 
-template <typename T, int N, bool ROW>
+template <typename T, int N, bool ROW, bool PERSIST>
 static void* pass_kernel() {
-  return ROW ? reinterpret_cast<void*>(k_row_pass<T, N>) : reinterpret_cast<void*>(k_col_pass<T, N>);
+  return ROW ? reinterpret_cast<void*>(k_row_pass<T, N, PERSIST>) : reinterpret_cast<void*>(k_col_pass<T, N, PERSIST>);
+}
+
+template <typename T, int N, bool ROW>
+static sofft_status pass_set_lds(size_t lds) {
+  sofft_status st = ROW ? set_lds(k_row_pass<T, N, false>, lds) : set_lds(k_col_pass<T, N, false>, lds);
+  if (st == SOFFT_OK) st = ROW ? set_lds(k_row_pass<T, N, true>, lds) : set_lds(k_col_pass<T, N, true>, lds);
+  return st;
 }
 
 // One pass over the lines of every run in a (row pass if ROW, else column
@@ -614,7 +646,9 @@ static void* pass_kernel() {
 template <typename T, int N, bool ROW>
 static sofft_status pass(PassArgs<T> a, PassLaunch cfg, hipStream_t s, Timing* tm) {
   constexpr int TPL = N / Shape<N>::P;
-  constexpr int maxt = block_threads<N, ROW ? kRowThreads : kColThreads>();
+  const bool want_persist = cfg.grid > 0;
+  const int maxt = want_persist ? kernel_threads<N, ROW ? kRowThreads : kColThreads, true>()
+                                : kernel_threads<N, ROW ? kRowThreads : kColThreads, false>();
   const int threads = cfg.threads > 0 ? std::min(cfg.threads, maxt) : maxt;
   size_t lds = 0;
   const int lpb = lines_per_block<T, N>(threads, a.lds_line, &lds);
@@ -622,16 +656,24 @@ static sofft_status pass(PassArgs<T> a, PassLaunch cfg, hipStream_t s, Timing* t
     set_error("ECS strip too long for the LDS budget");
     return SOFFT_EUNSUPPORTED;
   }
-  sofft_status st = ROW ? set_lds(k_row_pass<T, N>, lds) : set_lds(k_col_pass<T, N>, lds);
+  sofft_status st = pass_set_lds<T, N, ROW>(lds);
   if (st != SOFFT_OK) return st;
   const int lines = a.nruns * (ROW ? a.ny : a.nx);
   a.ntiles = (lines + lpb - 1) / lpb;
-  const int blocks = cfg.grid > 0 ? std::min(cfg.grid, a.ntiles) : a.ntiles;
+  const bool persist = want_persist && cfg.grid < a.ntiles;
+  const int blocks = persist ? cfg.grid : a.ntiles;
   if (tm && (st = tm->begin(ROW ? SOFFT_KERNEL_ROW : SOFFT_KERNEL_COL, s)) != SOFFT_OK) return st;
-  if (ROW)
-    k_row_pass<T, N><<<blocks, lpb * TPL, lds, s>>>(a);
-  else
-    k_col_pass<T, N><<<blocks, lpb * TPL, lds, s>>>(a);
+  if (ROW) {
+    if (persist)
+      k_row_pass<T, N, true><<<blocks, lpb * TPL, lds, s>>>(a);
+    else
+      k_row_pass<T, N, false><<<blocks, lpb * TPL, lds, s>>>(a);
+  } else {
+    if (persist)
+      k_col_pass<T, N, true><<<blocks, lpb * TPL, lds, s>>>(a);
+    else
+      k_col_pass<T, N, false><<<blocks, lpb * TPL, lds, s>>>(a);
+  }
   SOFFT_HIP_TRY(hipGetLastError());
   return tm ? tm->end(s) : SOFFT_OK;
 }
@@ -640,7 +682,7 @@ static sofft_status pass(PassArgs<T> a, PassLaunch cfg, hipStream_t s, Timing* t
 template <typename T, int N, bool ROW>
 static sofft_status pass_occupancy(int lds_line, int threads, int* blocks_per_cu, int* block_threads_out) {
   constexpr int TPL = N / Shape<N>::P;
-  constexpr int maxt = block_threads<N, ROW ? kRowThreads : kColThreads>();
+  constexpr int maxt = kernel_threads<N, ROW ? kRowThreads : kColThreads, true>();
   threads = threads > 0 ? std::min(threads, maxt) : maxt;
   size_t lds = 0;
   const int lpb = lines_per_block<T, N>(threads, lds_line, &lds);
@@ -648,10 +690,10 @@ static sofft_status pass_occupancy(int lds_line, int threads, int* blocks_per_cu
     set_error("ECS strip too long for the LDS budget");
     return SOFFT_EUNSUPPORTED;
   }
-  sofft_status st = ROW ? set_lds(k_row_pass<T, N>, lds) : set_lds(k_col_pass<T, N>, lds);
+  sofft_status st = pass_set_lds<T, N, ROW>(lds);
   if (st != SOFFT_OK) return st;
   int nb = 0;
-  SOFFT_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pass_kernel<T, N, ROW>(), lpb * TPL, lds));
+  SOFFT_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pass_kernel<T, N, ROW, true>(), lpb * TPL, lds));
   *blocks_per_cu = nb;
   *block_threads_out = lpb * TPL;
   return SOFFT_OK;
