@@ -116,7 +116,7 @@ typedef struct {
   int32_t iterations;    /* COCG iterations (all restarts included) */
   int32_t status;        /* SOFFT_OK, SOFFT_NOT_CONVERGED or SOFFT_BREAKDOWN */
   int32_t restarts;      /* restarts from the true residual */
-  int32_t reserved_;
+  int32_t fell_back;     /* learned solve only: 1 if it switched to the plain preconditioner */
   double rel_residual;   /* ||f - A x|| / ||f||, recomputed from x (Hermitian 2-norm) */
 } sofft_solve_stats;
 
@@ -192,6 +192,62 @@ sofft_status sofft_batch_set_launch_shape(sofft_batch* b, int32_t run, int32_t p
                                           int32_t grid);
 sofft_status sofft_batch_launch_shape(const sofft_batch* b, int32_t run, int32_t pass, int32_t* threads,
                                       int32_t* grid);
+
+/* ------------------------------------------------------------------ learned correction
+ * An addition to the method (not from the paper): a small network N corrects
+ * the FFT preconditioner of Eq. PreconFFT,
+ *     z = P^-1 r + s N(r/s, P^-1 r/s),   s = sqrt(mean |r|^2),
+ * N = three periodic 3x3 convolutions with 4 -> 16 -> 16 -> 2 channels and a
+ * ReLU after the first two.  Its inputs are Re and Im of r/s and of
+ * P^-1 r/s; its outputs are Re and Im of the correction.  Activations are
+ * FP16; the forward convolutions run on the matrix cores with FP32
+ * accumulation; weights are kept as FP32 master values and used as FP16.
+ * Parameters (sofft_lp_param_count() floats, host order): W1[9][16][4], b1[16],
+ * W2[9][16][16], b2[16], W3[9][2][16], b3[2], with tap t = 3 (dy + 1) + dx + 1
+ * reading the input at (y + dy, x + dx), periodic.  Grid widths must be
+ * multiples of 16. */
+typedef struct sofft_lp sofft_lp;
+
+/* A network with zero weights (a zero correction).  It owns its weights,
+ * Adam moments and activation buffers (grown on demand). */
+sofft_status sofft_lp_create(sofft_lp** out);
+sofft_status sofft_lp_destroy(sofft_lp* lp);
+int32_t sofft_lp_param_count(void);
+
+/* Copy the parameters from / to host memory (FP32, layout above).  Setting
+ * them also clears the Adam moments. */
+sofft_status sofft_lp_set_weights(sofft_lp* lp, const float* host);
+sofft_status sofft_lp_get_weights(const sofft_lp* lp, float* host);
+
+/* Forward pass on batch items b < batch: r and pz (= P^-1 r) device complex128
+ * [batch][ny][nx]; out device FP32 [batch][ny][nx][2] (N's output, before the
+ * scaling by s).  Asynchronous. */
+sofft_status sofft_lp_forward(sofft_lp* lp, const void* r, const void* pz, int64_t ny, int64_t nx, int32_t batch,
+                              float* out, void* stream);
+
+/* Loss and gradient of one batch: loss = mean over items, pixels and the two
+ * channels of (N - (e - pz)/s)^2; grad device FP32 [param_count], loss host.
+ * Blocking. */
+sofft_status sofft_lp_loss_grad(sofft_lp* lp, const void* r, const void* pz, const void* e, int64_t ny,
+                                int64_t nx, int32_t batch, float* grad, double* loss, void* stream);
+
+/* Train on npairs (residual r_k, error e_k = x* - x_k) pairs of the plan's
+ * grid, pair k at energy E_host[k] (P^-1 r is formed at that energy):
+ * `epochs` passes over shuffled batches of `batch` pairs (order drawn from
+ * `seed`), Adam with learning rate lr.  r, e: device complex128
+ * [npairs][ny][nx].  loss_host: epochs entries (mean batch loss), may be NULL.
+ * Blocking. */
+sofft_status sofft_lp_train(sofft_lp* lp, sofft_plan* plan, const void* r, const void* e, const double* E_host,
+                            int64_t npairs, int32_t epochs, int32_t batch, double lr, uint64_t seed,
+                            double* loss_host, void* stream);
+
+/* sofft_sse_solve with the corrected preconditioner in flexible COCG
+ * (beta = r_{k+1}^T (z_{k+1} - z_k) / rho_k).  An energy whose recurrence
+ * residual has not reached a new minimum for `patience` iterations continues
+ * with the plain preconditioner from its true residual (stats.fell_back = 1). */
+sofft_status sofft_sse_solve_learned(sofft_plan* plan, sofft_lp* lp, const void* f, int32_t f_per_energy,
+                                     const double* E_host, int32_t nE, double field, void* x_out, double rtol,
+                                     int32_t maxit, int32_t patience, sofft_solve_stats* stats, void* stream);
 
 /* Kernels whose launches can be timed (see sofft_timing_*). */
 typedef enum {

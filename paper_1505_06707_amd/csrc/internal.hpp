@@ -129,9 +129,16 @@ sofft_status launch_norm2_runs(const void* const* runs_dev, int nruns, int64_t n
                                double* partials, hipStream_t s);
 bool supported_length(int64_t n);
 
-// Stationary solver (sse.hip).
+// Learned correction network (learned.hip).
+struct LpNet;
+sofft_status lp_apply(LpNet& net, const cx<double>* r, cx<double>* z, int B, int H, int W, const int* active,
+                      const double* scale, hipStream_t s);
+
+// Stationary solver (sse.hip).  lp = null: plain FFT preconditioner (COCG);
+// otherwise flexible COCG with the learned correction and the fallback.
 sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E_host, int nE, double field,
-                       void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s);
+                       void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s,
+                       LpNet* lp = nullptr, int patience = 0);
 sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s);
 
 }  // namespace sofft

@@ -41,6 +41,9 @@ struct CocgScalars {
   cx<double> rho, alpha, beta;
   double rr, ff, true_res;
   int state, iters, first, restarts;
+  // flexible COCG with the learned correction
+  double best_rr;
+  int since, fell_back, fb_pending, pad_;
 };
 
 struct SseArgs {
@@ -68,6 +71,11 @@ struct SseArgs {
   const cx<double>* cx_strip;  // [C_{j,j-1} | C_{j,j} | C_{j,j+1}] on the x-strip
   const cx<double>* cy_strip;
   int lds_line_x, lds_line_y;
+  // learned correction (flexible COCG): off when learned = 0
+  int learned, patience;
+  cx<double>* part_rzo;        // [nE][nblk_row]: r^T z_old
+  int* active;                 // [nE]: energies the network corrects this round
+  double* lp_scale;            // [nE]: rms of r
 };
 
 enum RowMode : int { kRowIter = 0, kRowTrue = 1 };          // K1: input p (updated) or x
@@ -337,15 +345,48 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_row_prec(SseArgs a, int wan
     rv[s] = live ? a.r[off + t + TPL * s] : cx<double>{0.0, 0.0};
   }
   fft<double, N, +1>(v, L, t, a.twx);
-  cx<double> dot{0.0, 0.0};
+  cx<double> dot{0.0, 0.0}, dot_old{0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < P; ++s) {
     if (live) {
+      if (a.learned) dot_old = cfma(dot_old, rv[s], a.z[off + t + TPL * s]);   // r^T z of the last iteration
       a.z[off + t + TPL * s] = v[s];
       dot = cfma(dot, rv[s], v[s]);   // r^T z, unconjugated
     }
   }
   const cx<double> sum = block_sum(dot, lines);
+  if (threadIdx.x == 0) a.part_rz[size_t(e) * a.nblk_row + blockIdx.x] = sum;
+  if (a.learned) {
+    const cx<double> so = block_sum(dot_old, lines);
+    if (threadIdx.x == 0) a.part_rzo[size_t(e) * a.nblk_row + blockIdx.x] = so;
+  }
+}
+
+// ---------------------------------------------------------------- learned correction hooks
+// active[e] = the network corrects z of energy e in this round; lp_scale[e] =
+// rms of r from the partial sums of ||r||^2.
+__global__ void k_sse_lp_gate(SseArgs a, int want) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.nE) return;
+  const CocgScalars& sc = a.sc[e];
+  const bool on = sc.state == want && !sc.fell_back;
+  double rr = 0.0;
+  for (int b = 0; b < a.nblk_row; ++b) rr += a.part_rr[size_t(e) * a.nblk_row + b];
+  a.active[e] = (on && rr > 0.0) ? 1 : 0;
+  a.lp_scale[e] = sqrt(rr / double(a.vec));
+}
+
+// part_rz[e][b] = r^T z over block b's share of the grid, for the corrected energies.
+__global__ void __launch_bounds__(256) k_sse_lp_dot(SseArgs a) {
+  __shared__ cx<double> red[4];
+  const int e = blockIdx.y;
+  if (!a.active[e]) return;
+  const size_t per = (a.vec + gridDim.x - 1) / gridDim.x;
+  const size_t i0 = per * blockIdx.x, i1 = i0 + per < a.vec ? i0 + per : a.vec;
+  cx<double> dot{0.0, 0.0};
+  for (size_t i = i0 + threadIdx.x; i < i1; i += blockDim.x)
+    dot = cfma(dot, a.r[size_t(e) * a.vec + i], a.z[size_t(e) * a.vec + i]);
+  const cx<double> sum = block_sum(dot, red);
   if (threadIdx.x == 0) a.part_rz[size_t(e) * a.nblk_row + blockIdx.x] = sum;
 }
 
@@ -377,6 +418,10 @@ __global__ void k_sse_init(SseArgs a) {
   sc.true_res = 1.0;
   sc.state = ff > 0.0 ? int(kActive) : int(kDone);
   if (ff == 0.0) sc.true_res = 0.0;
+  sc.best_rr = ff;
+  sc.since = 0;
+  sc.fell_back = 0;
+  sc.fb_pending = 0;
 }
 
 // alpha = rho / p^T w.
@@ -423,6 +468,25 @@ __global__ void k_sse_beta(SseArgs a, double rtol, int maxit) {
     sc.state = kBreakdown;
     return;
   }
+  if (a.learned && !sc.fell_back) {
+    // flexible beta = r^T (z - z_old) / rho; fall back to the plain
+    // preconditioner (from the true residual) after `patience` iterations
+    // without a new minimum of ||r||
+    if (rr < sc.best_rr) {
+      sc.best_rr = rr;
+      sc.since = 0;
+    } else if (++sc.since >= a.patience) {
+      sc.fell_back = 1;
+      sc.fb_pending = 1;
+      sc.state = kCheck;
+      return;
+    }
+    cx<double> rzo{0.0, 0.0};
+    for (int b = 0; b < a.nblk_row; ++b) rzo = rzo + a.part_rzo[size_t(e) * a.nblk_row + b];
+    sc.beta = cdiv(rz - rzo, sc.rho);
+    sc.rho = rz;
+    return;
+  }
   sc.beta = cdiv(rz, sc.rho);
   sc.rho = rz;
 }
@@ -441,15 +505,19 @@ __global__ void k_sse_true(SseArgs a, double rtol, int maxit) {
     rz = rz + a.part_rz[size_t(e) * a.nblk_row + b];
   }
   sc.true_res = sqrt(rr / sc.ff);
+  const int fb = sc.fb_pending;
+  sc.fb_pending = 0;
   if (rr <= rtol * rtol * sc.ff) {
     sc.state = kDone;
-  } else if (sc.iters >= maxit || sc.restarts >= 8) {
+  } else if (sc.iters >= maxit || (!fb && sc.restarts >= 8)) {
     sc.state = kMaxit;
   } else {
     sc.rr = rr;
     sc.rho = rz;
     sc.first = 1;
-    sc.restarts += 1;
+    if (!fb) sc.restarts += 1;
+    sc.best_rr = rr;
+    sc.since = 0;
     sc.state = kActive;
   }
 }
@@ -571,8 +639,9 @@ static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipSt
   const int nbr = int((Y.n + sse_lpb(X.n, llx) - 1) / sse_lpb(X.n, llx));
   const int nbc = int((X.n + sse_lpb(Y.n, lly) - 1) / sse_lpb(Y.n, lly));
   const size_t bytes_vec = vec * sizeof(cx<double>);
-  const size_t need = 5 * bytes_vec * nE + bytes_vec + size_t(nE) * nbr * (sizeof(double) + sizeof(cx<double>)) +
-                      size_t(nE) * nbc * sizeof(cx<double>) + size_t(nE) * sizeof(CocgScalars) + 4096;
+  const size_t need = 5 * bytes_vec * nE + bytes_vec + size_t(nE) * nbr * (sizeof(double) + 2 * sizeof(cx<double>)) +
+                      size_t(nE) * nbc * sizeof(cx<double>) + size_t(nE) * sizeof(CocgScalars) +
+                      size_t(nE) * (sizeof(int) + sizeof(double)) + 8192;
   if (!p.sse_ws.p || p.sse_ws.bytes < need) {
     dev_free(p.sse_ws);
     if (hipMalloc(&p.sse_ws.p, need) != hipSuccess) {
@@ -603,6 +672,9 @@ static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipSt
   a.part_rz = reinterpret_cast<cx<double>*>(take(sizeof(cx<double>) * nE * nbr));
   a.part_pw = reinterpret_cast<cx<double>*>(take(sizeof(cx<double>) * nE * nbc));
   a.sc = reinterpret_cast<CocgScalars*>(take(sizeof(CocgScalars) * nE));
+  a.part_rzo = reinterpret_cast<cx<double>*>(take(sizeof(cx<double>) * nE * nbr));
+  a.active = reinterpret_cast<int*>(take(sizeof(int) * nE));
+  a.lp_scale = reinterpret_cast<double*>(take(sizeof(double) * nE));
   a.nblk_row = nbr;
   a.nblk_col = nbc;
   a.twx = static_cast<const cx<double>*>(X.tw64.p);
@@ -639,11 +711,14 @@ static sofft_status sse_check_plan(const Plan& p) {
 }
 
 sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E_host, int nE, double field,
-                       void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s) {
+                       void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s, LpNet* lp,
+                       int patience) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
   SseArgs a{};
   if ((st = sse_prepare(p, nE, field, a, s)) != SOFFT_OK) return st;
+  a.learned = lp ? 1 : 0;
+  a.patience = patience;
   a.x = static_cast<cx<double>*>(x_out);
   a.f = static_cast<const cx<double>*>(f);
   a.f_per_energy = f_per_energy;
@@ -662,6 +737,17 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
   SseLauncher L = sse_launcher(p.ax[0].n, p.ax[1].n);
   Timing& tm = p.timing;
   const int sb = (nE + 63) / 64;
+  // learned correction of z = P^-1 r for the energies in state `want`, then r^T z
+  auto correct = [&](int want) -> sofft_status {
+    if (!lp) return SOFFT_OK;
+    k_sse_lp_gate<<<sb, 64, 0, s>>>(a, want);
+    SOFFT_HIP_TRY(hipGetLastError());
+    sofft_status q = lp_apply(*lp, a.r, a.z, nE, a.ny, a.nx, a.active, a.lp_scale, s);
+    if (q != SOFFT_OK) return q;
+    k_sse_lp_dot<<<dim3(a.nblk_row, nE), 256, 0, s>>>(a);
+    SOFFT_HIP_TRY(hipGetLastError());
+    return SOFFT_OK;
+  };
   // r = f, x = 0, z = P^-1 r, rho = r^T z: run the set-up kernels on every
   // energy by marking them active first.
   std::vector<CocgScalars> init(nE);
@@ -673,6 +759,7 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
   if ((st = L(kK4, a, kActive, kUpdInit, s, tm)) != SOFFT_OK) return st;
   if ((st = L(kK5, a, kActive, 0, s, tm)) != SOFFT_OK) return st;
   if ((st = L(kK6, a, kActive, 0, s, tm)) != SOFFT_OK) return st;
+  if ((st = correct(kActive)) != SOFFT_OK) return st;
   k_sse_init<<<sb, 64, 0, s>>>(a);
   SOFFT_HIP_TRY(hipGetLastError());
 
@@ -688,6 +775,7 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
       if ((st = L(kK4, a, kActive, kUpdIter, s, tm)) != SOFFT_OK) return st;
       if ((st = L(kK5, a, kActive, 0, s, tm)) != SOFFT_OK) return st;
       if ((st = L(kK6, a, kActive, 0, s, tm)) != SOFFT_OK) return st;
+      if ((st = correct(kActive)) != SOFFT_OK) return st;
       k_sse_beta<<<sb, 64, 0, s>>>(a, rtol, maxit);
       SOFFT_HIP_TRY(hipGetLastError());
       if ((it + 1) % poll == 0) {
@@ -704,6 +792,7 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
     if ((st = L(kK4, a, kCheck, kUpdTrue, s, tm)) != SOFFT_OK) return st;
     if ((st = L(kK5, a, kCheck, 0, s, tm)) != SOFFT_OK) return st;
     if ((st = L(kK6, a, kCheck, 0, s, tm)) != SOFFT_OK) return st;
+    if ((st = correct(kCheck)) != SOFFT_OK) return st;
     k_sse_true<<<sb, 64, 0, s>>>(a, rtol, maxit);
     SOFFT_HIP_TRY(hipGetLastError());
     SOFFT_HIP_TRY(hipMemcpyAsync(host.data(), a.sc, sizeof(CocgScalars) * nE, hipMemcpyDeviceToHost, s));
@@ -723,6 +812,7 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
       stats[e].status = code;
       stats[e].rel_residual = c.state == kBreakdown ? std::sqrt(c.rr / c.ff) : c.true_res;
       stats[e].restarts = c.restarts;
+      stats[e].fell_back = c.fell_back;
     }
     if (code != SOFFT_OK && worst == SOFFT_OK) worst = sofft_status(code);
   }

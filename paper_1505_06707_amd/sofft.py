@@ -31,7 +31,7 @@ class SolveStats(ctypes.Structure):
         ("iterations", ctypes.c_int32),
         ("status", ctypes.c_int32),
         ("restarts", ctypes.c_int32),
-        ("reserved_", ctypes.c_int32),
+        ("fell_back", ctypes.c_int32),
         ("rel_residual", ctypes.c_double),
     ]
 
@@ -78,6 +78,23 @@ _SIGS = {
                                                     ctypes.c_int32, ctypes.c_int32]),
     "sofft_batch_launch_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "sofft_lp_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
+    "sofft_lp_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sofft_lp_param_count": (ctypes.c_int32, []),
+    "sofft_lp_set_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_lp_get_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_lp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_lp_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "sofft_lp_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_sse_solve_learned": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                                               ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
     "sofft_timing_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "sofft_timing_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
@@ -240,6 +257,27 @@ class Plan:
                      rel_residual=s.rel_residual) for s in stats]
         return out, rows, code
 
+    def sse_solve_learned(self, lp, f, energies, field=0.0, rtol=1e-8, maxit=10000, patience=30, out=None,
+                          stream=None):
+        """sse_solve with the learned correction in flexible COCG; returns
+        (x, stats, status), stats rows also carrying 'fell_back'."""
+        import torch
+        E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
+        nE = len(E)
+        per = 1 if f.numel() == nE * self.numel and nE > 1 else 0
+        fptr = _dev_ptr(f, torch.complex128, self.numel * (nE if per else 1), "f")
+        if out is None:
+            out = torch.empty((nE,) + self.shape, dtype=torch.complex128, device=f.device)
+        optr = _dev_ptr(out, torch.complex128, nE * self.numel, "out")
+        stats = (SolveStats * nE)()
+        code = lib().sofft_sse_solve_learned(self._h, lp._h, fptr, per, E.ctypes.data_as(ctypes.c_void_p), nE,
+                                             float(field), optr, float(rtol), int(maxit), int(patience), stats,
+                                             _stream(stream))
+        _check(code)
+        rows = [dict(iterations=s.iterations, status=s.status, restarts=s.restarts, fell_back=s.fell_back,
+                     rel_residual=s.rel_residual) for s in stats]
+        return out, rows, code
+
     def norm2(self, psi, stream=None):
         ptr = _dev_ptr(psi, self.torch_dtype, self.numel, "psi")
         out = ctypes.c_double()
@@ -327,3 +365,73 @@ class Batch:
         g = ctypes.c_int32()
         _check(lib().sofft_batch_launch_shape(self._h, int(run), int(pass_), ctypes.byref(t), ctypes.byref(g)))
         return t.value, g.value
+
+
+class LearnedCorrection:
+    """The correction network of sofft_lp_* (weights as one FP32 vector in the
+    layout of include/sofft.h)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().sofft_lp_create(ctypes.byref(h)))
+        self._h = h
+        self.nparams = int(lib().sofft_lp_param_count())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sofft_lp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float32).ravel())
+        if w.size != self.nparams:
+            raise ValueError(f"{self.nparams} parameters expected, got {w.size}")
+        _check(lib().sofft_lp_set_weights(self._h, w.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_weights(self):
+        w = np.empty(self.nparams, dtype=np.float32)
+        _check(lib().sofft_lp_get_weights(self._h, w.ctypes.data_as(ctypes.c_void_p)))
+        return w
+
+    def forward(self, r, pz, stream=None):
+        """N's output [B][ny][nx][2] (float32 device tensor) for complex128 r, pz [B][ny][nx]."""
+        import torch
+        B, ny, nx = r.shape
+        out = torch.empty((B, ny, nx, 2), dtype=torch.float32, device=r.device)
+        _check(lib().sofft_lp_forward(self._h, _dev_ptr(r, torch.complex128, r.numel(), "r"),
+                                      _dev_ptr(pz, torch.complex128, r.numel(), "pz"), ny, nx, B,
+                                      _dev_ptr(out, torch.float32, out.numel(), "out"), _stream(stream)))
+        return out
+
+    def loss_grad(self, r, pz, e, stream=None):
+        """(loss, gradient as a numpy float32 vector) of one batch."""
+        import torch
+        B, ny, nx = r.shape
+        g = torch.empty(self.nparams, dtype=torch.float32, device=r.device)
+        loss = ctypes.c_double()
+        _check(lib().sofft_lp_loss_grad(self._h, _dev_ptr(r, torch.complex128, r.numel(), "r"),
+                                        _dev_ptr(pz, torch.complex128, r.numel(), "pz"),
+                                        _dev_ptr(e, torch.complex128, r.numel(), "e"), ny, nx, B,
+                                        _dev_ptr(g, torch.float32, g.numel(), "grad"), ctypes.byref(loss),
+                                        _stream(stream)))
+        return loss.value, g.cpu().numpy()
+
+    def train(self, plan, r, e, energies, epochs, batch, lr=1e-3, seed=0, stream=None):
+        """Train on (r_k, e_k) pairs [npairs][ny][nx] of the plan's grid; returns the per-epoch losses."""
+        import torch
+        E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
+        n = r.shape[0]
+        if len(E) != n:
+            raise ValueError("one energy per pair is needed")
+        losses = np.zeros(epochs, dtype=np.float64)
+        _check(lib().sofft_lp_train(self._h, plan._h, _dev_ptr(r, torch.complex128, r.numel(), "r"),
+                                    _dev_ptr(e, torch.complex128, r.numel(), "e"),
+                                    E.ctypes.data_as(ctypes.c_void_p), n, int(epochs), int(batch), float(lr),
+                                    int(seed), losses.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return losses

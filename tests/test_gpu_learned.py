@@ -1,0 +1,145 @@
+"""GPU parity of the learned preconditioner correction (sofft_lp_*, via the
+C ABI) against the FP64 oracle (oracle.learned), and its use in flexible
+COCG.
+
+Tolerances: the forward pass stores FP16 activations on both sides and
+differs only by FP32 accumulation on the matrix cores (relative error
+~1e-7) and the rare FP16 rounding that this flips (one FP16 unit, 2^-11
+relative, in one activation): relative L2 <= 1e-3 of the output.  Gradients
+are accumulated in FP32/FP64 from the same FP16 activations: relative L2 <=
+1e-4 per layer.  Solves are checked by the oracle's true residual."""
+import numpy as np
+import pytest
+
+from oracle import learned as lo
+from oracle import sse as os_
+from oracle import tdse as ot
+from paper_1505_06707_amd import workloads as wl
+from paper_1505_06707_amd.lp_data import flat_params, make_pairs, unflat_params
+from tests.helpers import rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _sofft():
+    from paper_1505_06707_amd import sofft
+    return sofft
+
+
+def _params(seed):
+    ps = lo.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    return [(W, rng.normal(scale=0.05, size=b.shape)) for W, b in ps]
+
+
+def _fields(B, ny, nx, seed):
+    rng = np.random.default_rng(seed)
+    f = lambda: rng.normal(size=(B, ny, nx)) + 1j * rng.normal(size=(B, ny, nx))
+    return f(), f(), f()
+
+
+@pytest.mark.parametrize("B,ny,nx", [(2, 24, 48), (1, 64, 64), (3, 7, 16)])
+def test_forward_matches_oracle(B, ny, nx):
+    s = _sofft()
+    print(f"lp forward B={B} {ny}x{nx}", flush=True)
+    params = _params(1)
+    lp = s.LearnedCorrection()
+    lp.set_weights(flat_params(params))
+    assert np.array_equal(lp.get_weights(), flat_params(params))
+    r, pz, _ = _fields(B, ny, nx, 2)
+    out = lp.forward(torch.from_numpy(r).cuda(), torch.from_numpy(pz).cuda()).cpu().numpy()
+    scale = np.sqrt(np.mean(np.abs(r) ** 2, axis=(1, 2)))
+    y, _ = lo.forward(params, lo.features(r, pz, scale))
+    ref = np.moveaxis(y, 1, -1)
+    err = rel_l2(out, ref)
+    print(f"   rel L2 {err:.2e}", flush=True)
+    assert err < 1e-3
+    lp.close()
+
+
+@pytest.mark.parametrize("B,ny,nx", [(2, 16, 32), (1, 40, 48)])
+def test_loss_and_gradients_match_oracle(B, ny, nx):
+    s = _sofft()
+    print(f"lp loss/grad B={B} {ny}x{nx}", flush=True)
+    params = _params(3)
+    lp = s.LearnedCorrection()
+    lp.set_weights(flat_params(params))
+    r, pz, e = _fields(B, ny, nx, 4)
+    loss, g = lp.loss_grad(*(torch.from_numpy(a).cuda() for a in (r, pz, e)))
+    scale = np.sqrt(np.mean(np.abs(r) ** 2, axis=(1, 2)))
+    loss_o, grads_o = lo.loss_and_grads(params, r, pz, e, scale)
+    assert abs(loss - loss_o) <= 1e-5 * loss_o
+    gg = unflat_params(g)
+    for li in range(3):
+        for k in (0, 1):
+            err = rel_l2(gg[li][k], grads_o[li][k])
+            print(f"   layer {li} {'W' if k == 0 else 'b'}: rel L2 {err:.2e}", flush=True)
+            assert err < 1e-4
+    lp.close()
+
+
+def _sse_problem(n):
+    h = 0.2
+    L = n * h
+    return dict(n=n, L=L, R0=0.8 * L / 2)
+
+
+def _oracle_true_residual(n, E, f, x):
+    c = _sse_problem(n)
+    ax = ot.Axis(n, c["L"], R0=c["R0"], theta=0.5)
+    V = ot.softcore(1.0, 0.64, ax.z[None, :], ax.z[:, None])
+    op = os_.Operator((ax, ax), V, E)
+    return float(np.linalg.norm(f - op.matvec(x)) / np.linalg.norm(f))
+
+
+def test_zero_network_is_plain_cocg():
+    s = _sofft()
+    n = 64
+    c = _sse_problem(n)
+    plan = s.Plan([n, n], [c["L"]] * 2, R0=[c["R0"]] * 2, theta=0.5, charge=1.0, a2=0.64)
+    f = torch.from_numpy(-wl.smooth_source(n, n, seed=5)).cuda()
+    E = [0.1, 0.7, 1.4, 2.0]
+    lp = s.LearnedCorrection()
+    x0, st0, _ = plan.sse_solve(f, E, rtol=1e-10)
+    x1, st1, code = plan.sse_solve_learned(lp, f, E, rtol=1e-10, patience=50)
+    assert code == 0
+    # flexible beta keeps the term r_{k+1}^T z_k that vanishes only in exact
+    # arithmetic, so the two recurrences drift apart by a few iterations
+    for a, b in zip(st0, st1):
+        print(f"   plain {a['iterations']} flexible {b['iterations']}", flush=True)
+        assert abs(a["iterations"] - b["iterations"]) <= max(2, 0.1 * a["iterations"]) and b["fell_back"] == 0
+    assert rel_l2(x1.cpu().numpy(), x0.cpu().numpy()) < 1e-7
+    lp.close()
+    plan.close()
+
+
+def test_training_and_flexible_solve():
+    """Pairs from plain COCG, training on the GPU (loss must fall), then the
+    flexible solve on a held-out source: every energy converges (oracle true
+    residual), and the iteration counts against plain COCG are reported."""
+    s = _sofft()
+    n = 128
+    c = _sse_problem(n)
+    plan = s.Plan([n, n], [c["L"]] * 2, R0=[c["R0"]] * 2, theta=0.5, charge=1.0, a2=0.64)
+    train_src = [torch.from_numpy(-wl.smooth_source(n, n, seed=sd)).cuda() for sd in (1001, 1002)]
+    r, e, Es, iters = make_pairs(plan, train_src, [0.2, 0.8, 1.4, 2.0], schedule=(1, 3, 6, 12, 24, 48))
+    print(f"pairs {r.shape[0]} from {iters} plain iterations", flush=True)
+    lp = s.LearnedCorrection()
+    lp.set_weights(flat_params(lo.init_params(7)))
+    losses = lp.train(plan, r, e, Es, epochs=30, batch=4, lr=2e-3, seed=11)
+    print(f"   loss {losses[0]:.3e} -> {losses[-1]:.3e}", flush=True)
+    assert losses[-1] < 0.9 * losses[0]
+    f = torch.from_numpy(-wl.smooth_source(n, n, seed=2001)).cuda()
+    E = [0.05, 0.7, 1.35, 2.0]
+    _, st0, _ = plan.sse_solve(f, E, rtol=1e-8)
+    x1, st1, code = plan.sse_solve_learned(lp, f, E, rtol=1e-8, patience=30)
+    assert code == 0
+    fh = f.cpu().numpy()
+    for k, En in enumerate(E):
+        res = _oracle_true_residual(n, En, fh, x1[k].cpu().numpy())
+        print(f"   E={En}: plain {st0[k]['iterations']} learned {st1[k]['iterations']} "
+              f"(fell back: {st1[k]['fell_back']}), oracle true residual {res:.2e}", flush=True)
+        assert res <= 1e-8 * (1 + 1e-3)
+    lp.close()
+    plan.close()
