@@ -166,6 +166,52 @@ def gpu_batch(sofft, wl, torch, steps, seed=2024, warmup=40):
             "launch_shapes": {str(k): v for k, v in sorted(shapes.items())}, "graph_steps": 32}
 
 
+def gpu_learned(sofft, wl, torch, epochs=30):
+    """Learned correction on the 1024^2 x 64-energy stationary workload:
+    pairs from plain COCG on training sources, training on the GPU, then
+    plain COCG and the flexible solve on the evaluation source."""
+    from paper_1505_06707_amd.lp_data import init_weights, make_pairs
+    c = wl.LEARNED_2D
+    plan = sofft.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=c.theta, charge=c.charge, a2=c.a2)
+    t0 = time.perf_counter()
+    train_src = [torch.from_numpy(-wl.smooth_source(c.n, c.n, seed=sd)).cuda() for sd in (1001, 1002)]
+    r, e, Es, pair_its = make_pairs(plan, train_src, [0.2, 0.8, 1.4, 2.0], schedule=(1, 3, 6, 12, 24, 48))
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    lp = sofft.LearnedCorrection()
+    lp.set_weights(init_weights(7))
+    t0 = time.perf_counter()
+    losses = lp.train(plan, r, e, Es, epochs=epochs, batch=4, lr=2e-3, seed=11)
+    t_train = time.perf_counter() - t0
+    del r, e
+    f = torch.from_numpy(-wl.smooth_source(c.n, c.n, seed=0)).cuda()
+    E = c.energies()
+    out = torch.empty((len(E), c.n, c.n), dtype=torch.complex128, device="cuda")
+    plan.sse_solve(f, E[:2], rtol=c.rtol, out=out[:2])    # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st0, code0 = plan.sse_solve(f, E, rtol=c.rtol, out=out)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, st1, code1 = plan.sse_solve_learned(lp, f, E, rtol=c.rtol, patience=30, out=out)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    lp.close()
+    plan.close()
+    i0 = np.array([q["iterations"] for q in st0])
+    i1 = np.array([q["iterations"] for q in st1])
+    return {"workload": f"{c.n}^2 x {len(E)} energies, rtol {c.rtol}", "pairs": int(len(Es)),
+            "pair_plain_iterations": int(pair_its), "pairs_s": t_pairs, "train_s": t_train,
+            "loss_first_last": [float(losses[0]), float(losses[-1])],
+            "plain": {"time_s": t_plain, "status": int(code0), "iterations_mean": float(i0.mean()),
+                      "iterations_max": int(i0.max())},
+            "learned": {"time_s": t_learned, "status": int(code1), "iterations_mean": float(i1.mean()),
+                        "iterations_max": int(i1.max()), "fell_back": int(sum(q["fell_back"] for q in st1)),
+                        "max_true_rel_residual": float(max(q["rel_residual"] for q in st1))},
+            "gain_time": t_plain / t_learned, "gain_iterations": float(i0.mean() / i1.mean())}
+
+
 def cpu_baseline(wl, sample_steps, seed=1):
     """The FP64 oracle on the host, a bounded sample of the same workload."""
     from oracle import tdse as ot
@@ -195,6 +241,7 @@ def main():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--pcg-energies", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this size (counter calibration)")
@@ -271,6 +318,14 @@ def main():
         log(f"  {batch['ms_per_step']:.3f} ms/step for {batch['grid_points'] / 1e6:.1f} M points, "
             f"{batch['value'] / 1e9:.2f} G grid-point-steps/s, {batch['algorithmic_GBs']:.0f} GB/s algorithmic")
 
+    learned = None
+    if not args.no_learned:
+        log("learned correction: 1024^2 x 64 energies (pairs, training, plain vs flexible solve)")
+        learned = gpu_learned(sofft, wl, torch)
+        log(f"  plain {learned['plain']['time_s']:.2f} s (mean {learned['plain']['iterations_mean']:.0f} it), "
+            f"learned {learned['learned']['time_s']:.2f} s (mean {learned['learned']['iterations_mean']:.0f} it, "
+            f"{learned['learned']['fell_back']} fell back); training {learned['train_s']:.1f} s")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"CPU oracle sample: {args.cpu_sample_steps} steps")
@@ -299,6 +354,7 @@ def main():
         "fp32": fp32,
         "pcg": pcg,
         "batch": batch,
+        "learned": learned,
     }
     print(json.dumps(out), flush=True)
 

@@ -30,6 +30,20 @@ def make_pairs(plan, sources, energies, schedule=(1, 2, 4, 8, 16, 32, 64), rtol_
     return torch.stack(rs), torch.stack(es), np.array(Es), iters
 
 
+def init_weights(seed, layers=((4, 16), (16, 16), (16, 2))):
+    """Seeded initial parameters as one float32 vector in the library's order:
+    He-normal weights (std sqrt(2 / (9 cin))), the output layer scaled by 0.1,
+    zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for li, (cin, cout) in enumerate(layers):
+        W = rng.normal(scale=np.sqrt(2.0 / (9 * cin)), size=(9, cout, cin))
+        if li == len(layers) - 1:
+            W = W * 0.1
+        parts += [W.ravel(), np.zeros(cout)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 def flat_params(params):
     """Oracle-layout parameters [(W [9, cout, cin], b [cout]) x 3] as one
     float32 vector in the library's order."""
