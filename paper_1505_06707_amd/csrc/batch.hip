@@ -396,7 +396,12 @@ sofft_status sofft_batch_propagate(sofft_batch* b, void* const* psi, double dt, 
       tables_changed |= !had;
     }
   }
-  if (tables_changed) drop_graph(b);   // table addresses may have moved
+  for (BatchClass& c : b->cls) {
+    bool changed = false;
+    if ((st = ensure_vphase(plan_of(c.plan), dt, s, &changed)) != SOFFT_OK) return st;
+    tables_changed |= changed;
+  }
+  if (tables_changed) drop_graph(b);   // table addresses and dt-dependent arguments may have changed
   // State and field-row pointer tables of every class (ordered on s after the
   // work of earlier calls, which reads them).
   for (BatchClass& c : b->cls) {

@@ -229,18 +229,28 @@ sofft_status ensure_dt(Axis& a, double dt) {
       Bd[p] = 1.0 + ih * a.cdg[j];
       Cu[p] = p + 1 < m ? ih * a.cup[j] : 0.0;
     }
+    // B is strongly diagonally dominant for the usual dt, and each level
+    // squares the relative coupling: stop as soon as every remaining
+    // |a_p/b_p|, |c_p/b_p| is below 1e-18, where dropping the couplings
+    // changes u by less than FP64 rounding.  ceil(log2 m) levels at most.
     int levels = 0;
-    while ((int64_t(1) << levels) < m) ++levels;
-    std::vector<zc> al(size_t(levels) * m), ga(size_t(levels) * m);
-    for (int l = 0; l < levels; ++l) {
-      const int64_t s = int64_t(1) << l;
+    std::vector<zc> al, ga;
+    auto coupled = [&]() {
+      for (int64_t p = 0; p < m; ++p)
+        if (std::abs(A[p]) > 1e-18 * std::abs(Bd[p]) || std::abs(Cu[p]) > 1e-18 * std::abs(Bd[p])) return true;
+      return false;
+    };
+    while ((int64_t(1) << levels) < m && coupled()) {
+      const int64_t s = int64_t(1) << levels;
       std::vector<zc> A2(m), B2(m), C2(m);
+      al.resize(size_t(levels + 1) * m);
+      ga.resize(size_t(levels + 1) * m);
       for (int64_t p = 0; p < m; ++p) {
         const bool lo = p - s >= 0, hi = p + s < m;
         const zc alpha = lo ? A[p] / Bd[p - s] : 0.0;
         const zc gamma = hi ? Cu[p] / Bd[p + s] : 0.0;
-        al[size_t(l) * m + p] = alpha;
-        ga[size_t(l) * m + p] = gamma;
+        al[size_t(levels) * m + p] = alpha;
+        ga[size_t(levels) * m + p] = gamma;
         A2[p] = lo ? -alpha * A[p - s] : 0.0;
         C2[p] = hi ? -gamma * Cu[p + s] : 0.0;
         B2[p] = Bd[p] - (lo ? alpha * Cu[p - s] : 0.0) - (hi ? gamma * A[p + s] : 0.0);
@@ -248,6 +258,7 @@ sofft_status ensure_dt(Axis& a, double dt) {
       A.swap(A2);
       Bd.swap(B2);
       Cu.swap(C2);
+      ++levels;
     }
     std::vector<zc> bi(m);
     for (int64_t p = 0; p < m; ++p) bi[p] = 1.0 / Bd[p];
@@ -355,6 +366,7 @@ sofft_status sofft_plan_destroy(sofft_plan* plan) {
   dev_free(plan->partials);
   dev_free(plan->sse_ws);
   dev_free(plan->sse_E);
+  dev_free(plan->vphase);
   delete plan;
   return SOFFT_OK;
 }

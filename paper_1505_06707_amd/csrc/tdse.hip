@@ -53,6 +53,7 @@ struct PassArgs {
   const double* x;        // x nodes
   const cx<double>* zx;   // z(x_j)
   const cx<double>* zy;   // z(y_j) (2D) or null
+  const cx<double>* vph;  // 2D: exp(-i V0(z_x, z_y) dt/2) on the grid, [ny][nx]; null when V0 = 0
   int j0, m, levels;      // ECS strip of the pass axis
   int j0y, my;            // ECS strip of the y axis (row pass of a 2D grid)
   const cx<double>* alpha;
@@ -167,9 +168,12 @@ __device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const L
 #endif
 constexpr int kRowThreads = SOFFT_ROW_THREADS;
 constexpr int kColThreads = SOFFT_COL_THREADS;
+#ifndef SOFFT_MIN_WAVES_WIDE
+#define SOFFT_MIN_WAVES_WIDE 2
+#endif
 template <int N>
 constexpr int min_waves_per_simd() {
-  return Shape<N>::P == 4 ? 4 : 2;
+  return Shape<N>::P == 4 ? 4 : SOFFT_MIN_WAVES_WIDE;
 }
 // Threads per block: THREADS (P = 12 shapes at most 512, so that two waves
 // per SIMD leave them 256 VGPRs), and at least one whole line.
@@ -315,22 +319,19 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     cx<double> kin[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
-    // inputs of the potential, fetched before the transforms
-    cx<double> zxs[P];
+    // static potential phase and x of the field term, fetched before the transforms
+    cx<double> vps[P];
     double xs[P];
+    double f = 0.0;
     if (a.do_pot) {
+      const cx<double>* vrow = a.vph ? a.vph + size_t(crow) * N : nullptr;
 #pragma unroll
       for (int s = 0; s < P; ++s) {
-        zxs[s] = a.zx[t + TPL * s];
+        vps[s] = vrow ? vrow[t + TPL * s] : cx<double>{1.0, 0.0};
         xs[s] = a.x[t + TPL * s];
       }
-    }
-    double f = 0.0;
-    cx<double> zy{0.0, 0.0};
-    if (a.do_pot) {
       const double* fm = run_field(a, run);
       f = fm ? fm[step] : 0.0;
-      if (a.zy) zy = a.zy[crow];
     }
     fft<X, N, -1>(v, L, t, a.tw);
 #pragma unroll
@@ -341,12 +342,13 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
       // identity on them); rows on it get the first, the column pass the second.
       // On the x-strip the phase waits in LDS (from 2m) across the CN, or is
       // evaluated again after it when LDS holds FP32.
-      const cx<double> zy2a = cmul(zy, zy) + cx<double>{a.a2, 0.0};
+      // exp(-i U dt/2) = exp(-i V0 dt/2) exp(-i f x dt/2)
       const bool both = strip_pos_rt(crow, a.j0y, a.ny) >= a.my;
       const int m = a.m;
+      const double fh = f * a.ht;
 #pragma unroll
       for (int s = 0; s < P; ++s) {
-        const cx<double> ph = potential_phase(cmul(zxs[s], zxs[s]) + zy2a, a.charge, f * xs[s], a.ht);
+        const cx<double> ph = cmul(vps[s], expi(fh * xs[s], 0.0));
         const int p = strip_pos<N>(t + TPL * s, a.j0);
         if (p < m) {
           v[s] = cmul(v[s], ph);
@@ -369,7 +371,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
               if constexpr (park) {
                 v[s] = cmul(v[s], widen(L[2 * m + p]));
               } else {
-                v[s] = cmul(v[s], potential_phase(cmul(zxs[s], zxs[s]) + zy2a, a.charge, f * xs[s], a.ht));
+                v[s] = cmul(v[s], cmul(vps[s], expi(fh * xs[s], 0.0)));
               }
             }
           }
@@ -421,25 +423,21 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
       // C_y and the second potential half-step, on the y-strip only.
       const double* fm = run_field(a, run);
       const double f = fm ? fm[step] : 0.0;
-      const cx<double> zx = a.zx[ccol];
-      const double fx = f * a.x[ccol];
+      const cx<double> lph = expi(f * a.x[ccol] * a.ht, 0.0);   // exp(-i f x dt/2)
       const int m = a.m;
-#pragma unroll
-      for (int s = 0; s < P; ++s) {
-        const int p = strip_pos<N>(t + TPL * s, a.j0);
-        if (p < m) L[p] = narrow<X>(v[s]);
-      }
-      cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln, lpb}; });
-      const cx<double> zx2a = cmul(zx, zx) + cx<double>{a.a2, 0.0};
+      cx<double> vps[P];
 #pragma unroll
       for (int s = 0; s < P; ++s) {
         const int e = t + TPL * s;
         const int p = strip_pos<N>(e, a.j0);
-        if (p < m) {
-          const cx<double> zy = a.zy[e];
-          v[s] = cmul(2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s],
-                      potential_phase(zx2a + cmul(zy, zy), a.charge, fx, a.ht));
-        }
+        vps[s] = (p < m && a.vph) ? a.vph[size_t(e) * ld + ccol] : cx<double>{1.0, 0.0};
+        if (p < m) L[p] = narrow<X>(v[s]);
+      }
+      cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln, lpb}; });
+#pragma unroll
+      for (int s = 0; s < P; ++s) {
+        const int p = strip_pos<N>(t + TPL * s, a.j0);
+        if (p < m) v[s] = cmul(2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s], cmul(vps[s], lph));
       }
       __syncthreads();
     }
@@ -493,6 +491,15 @@ __global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const
   }
 #pragma unroll
   for (int s = 0; s < P; ++s) a.psi[t + TPL * s] = narrow<T>(v[s]);
+}
+
+// exp(-i V0(z_x, z_y) dt/2) on the grid (the static part of the potential phase).
+__global__ void __launch_bounds__(256) k_vphase(cx<double>* out, int nx, int ny, const cx<double>* zx,
+                                                const cx<double>* zy, double charge, double a2, double ht) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= size_t(nx) * ny) return;
+  const int jx = int(i % nx), jy = int(i / nx);
+  out[i] = potential_phase(cmul(zx[jx], zx[jx]) + cmul(zy[jy], zy[jy]) + cx<double>{a2, 0.0}, charge, 0.0, ht);
 }
 
 __global__ void k_step_add(int64_t* counter, int64_t delta, int set) {
@@ -566,6 +573,7 @@ static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   a.x = static_cast<const double*>(p.ax[0].x_dev.p);
   a.zx = static_cast<const cx<double>*>(p.ax[0].z_dev.p);
   a.zy = p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p) : nullptr;
+  a.vph = p.vphase_ht == 0.5 * dt ? static_cast<const cx<double>*>(p.vphase.p) : nullptr;
   a.j0 = int(A.j0);
   a.m = int(A.m);
   a.levels = A.levels;
@@ -739,9 +747,36 @@ static sofft_status occupancy_n(bool row, int n, int lds_line, int threads, int*
   return SOFFT_EUNSUPPORTED;
 }
 
+// The table of exp(-i V0 dt/2) for this dt (2D plans with a potential).
+sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
+  if (changed) *changed = false;
+  if (p.prob.ndim != 2 || p.prob.charge == 0.0 || p.vphase_ht == 0.5 * dt) return SOFFT_OK;
+  const int nx = int(p.ax[0].n), ny = int(p.ax[1].n);
+  const size_t bytes = size_t(nx) * ny * sizeof(cx<double>);
+  if (!p.vphase.p) {
+    if (hipMalloc(&p.vphase.p, bytes) != hipSuccess) {
+      p.vphase.p = nullptr;
+      set_error("hipMalloc of the potential-phase table failed");
+      return SOFFT_ENOMEM;
+    }
+    p.vphase.bytes = bytes;
+  }
+  const size_t n = size_t(nx) * ny;
+  k_vphase<<<unsigned((n + 255) / 256), 256, 0, s>>>(static_cast<cx<double>*>(p.vphase.p), nx, ny,
+                                                     static_cast<const cx<double>*>(p.ax[0].z_dev.p),
+                                                     static_cast<const cx<double>*>(p.ax[1].z_dev.p),
+                                                     p.prob.charge, p.prob.a2, 0.5 * dt);
+  SOFFT_HIP_TRY(hipGetLastError());
+  p.vphase_ht = 0.5 * dt;
+  if (changed) *changed = true;
+  return SOFFT_OK;
+}
+
 template <typename T>
 static sofft_status propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
                                  hipStream_t s) {
+  sofft_status st0 = ensure_vphase(p, dt, s, nullptr);
+  if (st0 != SOFFT_OK) return st0;
   PassArgs<T> ra = axis_args<T>(p, 0, psi, dt);
   PassArgs<T> ca = axis_args<T>(p, 1, psi, dt);
   ra.f_mid = ca.f_mid = f_mid;
