@@ -64,7 +64,7 @@ struct PassArgs {
 
 // Crank-Nicolson on the ECS strip of a line held by the whole block (1D):
 // y = 2 B^-1 v - v by parallel cyclic reduction, staged in the line's LDS
-// storage (buffers [0, m) and [m, 2m)).  As in pcr_wave, neighbours are read at
+// storage (buffers [0, m) and [m, 2m)).  As in pcr_line, neighbours are read at
 // clamped indices (the host zeroes the coefficients that reach past the strip)
 // and the next level's coefficients are fetched during the current level.
 template <typename T, int N, typename X>
@@ -199,26 +199,32 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Crank-Nicolson solve B u = v on one line's strip by one wavefront: parallel
-// cyclic reduction, lane owning positions p = lane + 64 i (i < 4: the host
-// keeps the 2D strips at m <= 256).  The host zeroes alpha where p - 2^l < 0
-// and gamma where p + 2^l >= m, so neighbours are read at clamped indices
+// Crank-Nicolson solve B u = v on one line's strip by parallel cyclic
+// reduction with the coefficients the host prepared (truncated once the
+// couplings fall below FP64 rounding).  The host zeroes alpha where p - 2^l <
+// 0 and gamma where p + 2^l >= m, so neighbours are read at clamped indices
 // without branches; the next level's coefficients are fetched while the
 // current level is reduced.  Levels ping-pong between [0, m) and [m, 2m); on
 // entry [0, m) holds v, on exit u is in the buffer cn_result(m, levels).
-constexpr int kPcrPos = 4;
+//
+// The positions of a line are split into groups of 64 (one per lane of a
+// wavefront); k wavefronts share the line, wavefront q taking groups q, q + k,
+// ... (the host keeps 2D strips at m <= 256, so at most 4 groups).  With k > 1
+// the levels are separated by block barriers, with k = 1 by wavefront ones.
+constexpr int kPcrGroups = 4;
 __host__ __device__ __forceinline__ int cn_result(int m, int levels) { return (levels & 1) ? 0 : m; }
 
 template <typename T, int N, typename X>
-__device__ __forceinline__ void pcr_wave(const LineLDS<X>& Lw, int lane, const PassArgs<T>& a) {
-  constexpr int W = N / 128 > 0 ? (N / 128 < kPcrPos ? N / 128 : kPcrPos) : 1;
+__device__ __forceinline__ void pcr_line(const LineLDS<X>& Lw, int lane, int q, int k, const PassArgs<T>& a) {
+  constexpr int W = N / 128 > 0 ? (N / 128 < kPcrGroups ? N / 128 : kPcrGroups) : 1;
   const int m = a.m, levels = a.levels;
+  const int ngroups = (m + 63) >> 6;
   int src = 0, dst = m;
   cx<double> al[W], ga[W];
 #pragma unroll
   for (int i = 0; i < W; ++i) {
-    const int p = min(lane + 64 * i, m - 1);
-    if (levels > 0) {
+    const int p = min(lane + 64 * (q + k * i), m - 1);
+    if (levels > 0 && q + k * i < ngroups) {
       al[i] = a.alpha[p];
       ga[i] = a.gamma[p];
     }
@@ -229,34 +235,47 @@ __device__ __forceinline__ void pcr_wave(const LineLDS<X>& Lw, int lane, const P
     const cx<double>* gan = a.gamma + size_t(l + 1 < levels ? l + 1 : l) * m;
 #pragma unroll
     for (int i = 0; i < W; ++i) {
-      const int p0 = lane + 64 * i, p = min(p0, m - 1);
-      const cx<double> d = widen(Lw[src + p]) - cmul(al[i], widen(Lw[src + max(p - st, 0)])) -
-                           cmul(ga[i], widen(Lw[src + min(p + st, m - 1)]));
-      al[i] = aln[p];
-      ga[i] = gan[p];
-      if (p0 < m) Lw[dst + p] = narrow<X>(d);
+      if (q + k * i < ngroups) {   // uniform over the wavefront
+        const int p0 = lane + 64 * (q + k * i), p = min(p0, m - 1);
+        const cx<double> d = widen(Lw[src + p]) - cmul(al[i], widen(Lw[src + max(p - st, 0)])) -
+                             cmul(ga[i], widen(Lw[src + min(p + st, m - 1)]));
+        al[i] = aln[p];
+        ga[i] = gan[p];
+        if (p0 < m) Lw[dst + p] = narrow<X>(d);
+      }
     }
-    wave_sync();
+    if (k > 1)
+      __syncthreads();
+    else
+      wave_sync();
     const int tmp = src;
     src = dst;
     dst = tmp;
   }
 #pragma unroll
   for (int i = 0; i < W; ++i) {
-    const int p0 = lane + 64 * i, p = min(p0, m - 1);
-    const cx<double> u = cmul(a.binv[p], widen(Lw[src + p]));
-    if (p0 < m) Lw[dst + p] = narrow<X>(u);
+    if (q + k * i < ngroups) {
+      const int p0 = lane + 64 * (q + k * i), p = min(p0, m - 1);
+      const cx<double> u = cmul(a.binv[p], widen(Lw[src + p]));
+      if (p0 < m) Lw[dst + p] = narrow<X>(u);
+    }
   }
 }
 
-// All lines of the block: wavefront w solves the strips of lines w, w +
-// nwaves, ...; line_of(ln) gives the LDS view of line ln.  Block barriers
-// before and after.
+// All lines of the block; line_of(ln) gives the LDS view of line ln.  With at
+// least as many wavefronts as lines (and a multiple of them) every wavefront
+// works on one line, k = nwaves / lines sharing it; otherwise wavefront w
+// solves lines w, w + nwaves, ... alone.  Block barriers before and after.
 template <typename T, int N, typename LineOf>
 __device__ __forceinline__ void cn_block(int lpb, const PassArgs<T>& a, LineOf line_of) {
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;   // whole wavefronts
-  for (int ln = w; ln < lpb; ln += nw) pcr_wave<T, N>(line_of(ln), lane, a);
+  if (nw >= lpb && nw % lpb == 0) {
+    const int k = nw / lpb;
+    pcr_line<T, N>(line_of(w / k), lane, w % k, k, a);
+  } else {
+    for (int ln = w; ln < lpb; ln += nw) pcr_line<T, N>(line_of(ln), lane, 0, 1, a);
+  }
   __syncthreads();
 }
 
@@ -416,9 +435,6 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
     cx<double> v[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = live ? widen(base[size_t(t + TPL * s) * ld]) : cx<double>{0.0, 0.0};
-    cx<double> kin[P];
-#pragma unroll
-    for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
     if (cn) {
       // C_y and the second potential half-step, on the y-strip only.
       const double* fm = run_field(a, run);
@@ -441,6 +457,9 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
       }
       __syncthreads();
     }
+    cx<double> kin[P];
+#pragma unroll
+    for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
     fft<X, N, -1>(v, L, t, a.tw);
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
