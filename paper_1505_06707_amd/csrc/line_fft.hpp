@@ -135,11 +135,28 @@ __device__ __forceinline__ cx<double> twiddle_mul(cx<double> a, cx<double> w) {
 // a rounded twiddle is the same operator error in every step, and adding its
 // residual after the rounded product does not remove it.
 
+// Twiddles of one rolled stage (stride ns = R0 << sh) for this thread's B =
+// P/RR butterflies: w[b][m-1] = tws[(m-1) ns + (j mod ns)], j = t + TPL b.
+template <int N>
+__device__ __forceinline__ void stage_twiddle_load(cx<double> (&w)[Shape<N>::P / Shape<N>::RR][Shape<N>::RR - 1],
+                                                   const cx<double>* __restrict__ tws, int t, int sh) {
+  constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, TPL = N / P, B = P / RR;
+  const int ns = R0 << sh;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int j = t + TPL * b;
+    const int k = j - ((j >> sh) / R0) * ns;
+#pragma unroll
+    for (int m = 1; m < RR; ++m) w[b][m - 1] = tws[(m - 1) * ns + k];
+  }
+}
+
 // One rolled stage of radix RR with stride ns = R0 << sh (sh = log2(RR) (s-1));
-// tws points at this stage's twiddle table.
+// w holds this stage's twiddles (stage_twiddle_load).
 template <typename X, int N, int SIGN, bool LAST>
 __device__ __forceinline__ void rolled_stage(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, int t,
-                                             const cx<double>* __restrict__ tws, int sh) {
+                                             const cx<double> (&w)[Shape<N>::P / Shape<N>::RR][Shape<N>::RR - 1],
+                                             int sh) {
   constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, TPL = N / P, B = P / RR;
   constexpr int PAD = Shape<N>::PAD;
   const int ns = R0 << sh;
@@ -152,7 +169,7 @@ __device__ __forceinline__ void rolled_stage(cx<double> (&v)[Shape<N>::P], const
 #pragma unroll
     for (int m = 0; m < RR; ++m) a[m] = v[b + m * B];
 #pragma unroll
-    for (int m = 1; m < RR; ++m) a[m] = twiddle_mul<SIGN>(a[m], tws[(m - 1) * ns + k]);
+    for (int m = 1; m < RR; ++m) a[m] = twiddle_mul<SIGN>(a[m], w[b][m - 1]);
     DFT<RR, SIGN, double>::run(a);
     if constexpr (LAST) {
 #pragma unroll
@@ -166,7 +183,8 @@ __device__ __forceinline__ void rolled_stage(cx<double> (&v)[Shape<N>::P], const
 }
 
 // In-place transform of the line held in v.  Every thread of the block must
-// call it (it contains block barriers).
+// call it (it contains block barriers).  The twiddles of each rolled stage are
+// fetched one stage ahead, so their latency hides behind the LDS exchange.
 template <typename X, int N, int SIGN>
 __device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, int t,
                                     const cx<double>* __restrict__ tw) {
@@ -174,6 +192,8 @@ __device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<
   constexpr int TPL = N / P, PAD = Shape<N>::PAD;
   constexpr int LR = RR == 4 ? 2 : (RR == 8 ? 3 : 4);   // log2(RR)
   static_assert(P % R0 == 0 && P % RR == 0, "bad shape");
+  cx<double> w[P / RR][RR - 1];
+  stage_twiddle_load<N>(w, tw, t, 0);
   {  // stage 0: radix R0, stride 1, no twiddles
     constexpr int B = P / R0;
 #pragma unroll
@@ -194,14 +214,15 @@ __device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<
   int off = 0;
 #pragma unroll 1
   for (int sh = 0; sh < LR * (K - 1); sh += LR) {
-    rolled_stage<X, N, SIGN, false>(v, L, t, tw + off, sh);
+    rolled_stage<X, N, SIGN, false>(v, L, t, w, sh);
     off += (RR - 1) * (R0 << sh);
+    stage_twiddle_load<N>(w, tw + off, t, sh + LR);   // next stage
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = widen(L.template padded<PAD>(t + TPL * s));
     __syncthreads();
   }
-  rolled_stage<X, N, SIGN, true>(v, L, t, tw + off, LR * (K - 1));
+  rolled_stage<X, N, SIGN, true>(v, L, t, w, LR * (K - 1));
 }
 
 // Copy the stage twiddle tables (N entries) from global memory to LDS (all
