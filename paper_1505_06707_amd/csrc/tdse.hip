@@ -441,19 +441,24 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
       const double f = fm ? fm[step] : 0.0;
       const cx<double> lph = expi(f * a.x[ccol] * a.ht, 0.0);   // exp(-i f x dt/2)
       const int m = a.m;
+      // The strips go to a contiguous area per column (odd stride 2m + 1), not
+      // the interleaved FFT layout: one wavefront's positions are then
+      // consecutive in LDS and the reduction is free of bank conflicts.
+      const int cstride = 2 * m + 1;
+      const LineLDS<X> Lc{lines, c * cstride, 1};
       cx<double> vps[P];
 #pragma unroll
       for (int s = 0; s < P; ++s) {
         const int e = t + TPL * s;
         const int p = strip_pos<N>(e, a.j0);
         vps[s] = (p < m && a.vph) ? a.vph[size_t(e) * ld + ccol] : cx<double>{1.0, 0.0};
-        if (p < m) L[p] = narrow<X>(v[s]);
+        if (p < m) Lc[p] = narrow<X>(v[s]);
       }
-      cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln, lpb}; });
+      cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln * cstride, 1}; });
 #pragma unroll
       for (int s = 0; s < P; ++s) {
         const int p = strip_pos<N>(t + TPL * s, a.j0);
-        if (p < m) v[s] = cmul(2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s], cmul(vps[s], lph));
+        if (p < m) v[s] = cmul(2.0 * widen(Lc[cn_result(m, a.levels) + p]) - v[s], cmul(vps[s], lph));
       }
       __syncthreads();
     }
