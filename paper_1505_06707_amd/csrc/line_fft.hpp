@@ -49,15 +49,16 @@ template <> struct Shape<1024> { static constexpr int P = 8,  R0 = 2, RR = 8, K 
 template <> struct Shape<2048> { static constexpr int P = 8,  R0 = 4, RR = 8, K = 3, PAD = 4; };
 template <> struct Shape<4096> { static constexpr int P = 8,  R0 = 8, RR = 8, K = 3, PAD = 8; };
 #else
-template <> struct Shape<16>   { static constexpr int P = 4,  R0 = 4, RR = 4, K = 1, PAD = 4; };
-template <> struct Shape<32>   { static constexpr int P = 4,  R0 = 2, RR = 4, K = 2, PAD = 2; };
-template <> struct Shape<64>   { static constexpr int P = 4,  R0 = 4, RR = 4, K = 2, PAD = 4; };
-template <> struct Shape<128>  { static constexpr int P = 4,  R0 = 2, RR = 4, K = 3, PAD = 2; };
-template <> struct Shape<256>  { static constexpr int P = 4,  R0 = 4, RR = 4, K = 3, PAD = 4; };
-template <> struct Shape<512>  { static constexpr int P = 4,  R0 = 2, RR = 4, K = 4, PAD = 2; };
-template <> struct Shape<1024> { static constexpr int P = 4,  R0 = 4, RR = 4, K = 4, PAD = 4; };
-template <> struct Shape<2048> { static constexpr int P = 4,  R0 = 2, RR = 4, K = 5, PAD = 2; };
-template <> struct Shape<4096> { static constexpr int P = 4,  R0 = 4, RR = 4, K = 5, PAD = 4; };
+// Radix-4 stages, no LDS padding (measured faster than one pad element per R0).
+template <> struct Shape<16>   { static constexpr int P = 4,  R0 = 4, RR = 4, K = 1, PAD = 0; };
+template <> struct Shape<32>   { static constexpr int P = 4,  R0 = 2, RR = 4, K = 2, PAD = 0; };
+template <> struct Shape<64>   { static constexpr int P = 4,  R0 = 4, RR = 4, K = 2, PAD = 0; };
+template <> struct Shape<128>  { static constexpr int P = 4,  R0 = 2, RR = 4, K = 3, PAD = 0; };
+template <> struct Shape<256>  { static constexpr int P = 4,  R0 = 4, RR = 4, K = 3, PAD = 0; };
+template <> struct Shape<512>  { static constexpr int P = 4,  R0 = 2, RR = 4, K = 4, PAD = 0; };
+template <> struct Shape<1024> { static constexpr int P = 4,  R0 = 4, RR = 4, K = 4, PAD = 0; };
+template <> struct Shape<2048> { static constexpr int P = 4,  R0 = 2, RR = 4, K = 5, PAD = 0; };
+template <> struct Shape<4096> { static constexpr int P = 4,  R0 = 4, RR = 4, K = 5, PAD = 0; };
 #endif
 template <> struct Shape<48>   { static constexpr int P = 12, R0 = 3, RR = 4, K = 2, PAD = 0; };
 template <> struct Shape<96>   { static constexpr int P = 12, R0 = 6, RR = 4, K = 2, PAD = 6; };
@@ -223,6 +224,51 @@ __device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<
     __syncthreads();
   }
   rolled_stage<X, N, SIGN, true>(v, L, t, w, LR * (K - 1));
+}
+
+// The same transform with two exchange buffers, L and Lb, used alternately:
+// a buffer is written again only two exchanges later, after a barrier every
+// thread passed once done reading it, so the barrier that follows each read
+// is dropped; one barrier at the end leaves both buffers free for the caller.
+template <typename X, int N, int SIGN>
+__device__ __forceinline__ void fft2(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, const LineLDS<X>& Lb,
+                                     int t, const cx<double>* __restrict__ tw) {
+  constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, K = Shape<N>::K;
+  constexpr int TPL = N / P, PAD = Shape<N>::PAD;
+  constexpr int LR = RR == 4 ? 2 : (RR == 8 ? 3 : 4);
+  cx<double> w[P / RR][RR - 1];
+  stage_twiddle_load<N>(w, tw, t, 0);
+  {
+    constexpr int B = P / R0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + TPL * b;
+      cx<double> a[R0];
+#pragma unroll
+      for (int m = 0; m < R0; ++m) a[m] = v[b + m * B];
+      DFT<R0, SIGN, double>::run(a);
+#pragma unroll
+      for (int m = 0; m < R0; ++m) L.template padded<PAD>(j * R0 + m) = narrow<X>(a[m]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = widen(L.template padded<PAD>(t + TPL * s));
+  }
+  int off = 0;
+  bool odd = true;
+#pragma unroll 1
+  for (int sh = 0; sh < LR * (K - 1); sh += LR) {
+    const LineLDS<X>& Lx = odd ? Lb : L;
+    rolled_stage<X, N, SIGN, false>(v, Lx, t, w, sh);
+    off += (RR - 1) * (R0 << sh);
+    stage_twiddle_load<N>(w, tw + off, t, sh + LR);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = widen(Lx.template padded<PAD>(t + TPL * s));
+    odd = !odd;
+  }
+  rolled_stage<X, N, SIGN, true>(v, L, t, w, LR * (K - 1));
+  __syncthreads();
 }
 
 // Copy the stage twiddle tables (N entries) from global memory to LDS (all

@@ -192,6 +192,14 @@ template <int N, bool PERSIST>
 constexpr int kernel_waves() {
   return PERSIST ? 2 : min_waves_per_simd<N>();
 }
+// Two LDS exchange buffers per line (fft2: one barrier per exchange instead of
+// two) when they fit the LDS budget at the largest block of a row or column pass.
+template <int N, typename X>
+constexpr int fft_buffers() {
+  constexpr int lines = block_threads<N, (kRowThreads > kColThreads ? kRowThreads : kColThreads)>() / (N / Shape<N>::P);
+  constexpr size_t bytes = size_t(2) * lines * fft_lds_elems<N>() * sizeof(cx<X>);
+  return (N <= 1024 && bytes <= 128 * 1024) ? 2 : 1;
+}
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -352,10 +360,18 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
       const double* fm = run_field(a, run);
       f = fm ? fm[step] : 0.0;
     }
-    fft<X, N, -1>(v, L, t, a.tw);
+    if constexpr (fft_buffers<N, X>() == 2) {
+      const LineLDS<X> Lb{lines, l * a.lds_line + fft_lds_elems<N>(), 1};
+      fft2<X, N, -1>(v, L, Lb, t, a.tw);
 #pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
-    fft<X, N, +1>(v, L, t, a.tw);
+      for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
+      fft2<X, N, +1>(v, L, Lb, t, a.tw);
+    } else {
+      fft<X, N, -1>(v, L, t, a.tw);
+#pragma unroll
+      for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
+      fft<X, N, +1>(v, L, t, a.tw);
+    }
     if (a.do_pot) {
       // Rows outside the y-strip get both potential half-steps here (C_y is the
       // identity on them); rows on it get the first, the column pass the second.
@@ -465,10 +481,18 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
     cx<double> kin[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
-    fft<X, N, -1>(v, L, t, a.tw);
+    if constexpr (fft_buffers<N, X>() == 2) {
+      const LineLDS<X> Lb{lines, c + fft_lds_elems<N>() * lpb, lpb};
+      fft2<X, N, -1>(v, L, Lb, t, a.tw);
 #pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
-    fft<X, N, +1>(v, L, t, a.tw);
+      for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
+      fft2<X, N, +1>(v, L, Lb, t, a.tw);
+    } else {
+      fft<X, N, -1>(v, L, t, a.tw);
+#pragma unroll
+      for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
+      fft<X, N, +1>(v, L, t, a.tw);
+    }
     if (live) {
 #pragma unroll
       for (int s = 0; s < P; ++s) base[size_t(t + TPL * s) * ld] = narrow<T>(v[s]);
@@ -568,11 +592,12 @@ __global__ void __launch_bounds__(256) k_norm2(const cx<T>* psi, int64_t n, doub
 
 // ---------------------------------------------------------------- launchers
 
+template <typename X>
 static int64_t lds_elems_for(int64_t n) {
   switch (n) {
 #define SOFFT_LDS_CASE(N) \
   case N:                 \
-    return fft_lds_elems<N>();
+    return fft_buffers<N, X>() * fft_lds_elems<N>();
     SOFFT_LDS_CASE(16) SOFFT_LDS_CASE(32) SOFFT_LDS_CASE(48) SOFFT_LDS_CASE(64) SOFFT_LDS_CASE(96)
     SOFFT_LDS_CASE(128) SOFFT_LDS_CASE(192) SOFFT_LDS_CASE(256) SOFFT_LDS_CASE(384) SOFFT_LDS_CASE(512)
     SOFFT_LDS_CASE(768) SOFFT_LDS_CASE(1024) SOFFT_LDS_CASE(2048) SOFFT_LDS_CASE(4096)
@@ -604,7 +629,7 @@ static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   a.alpha = static_cast<const cx<double>*>(A.alpha64.p);
   a.gamma = static_cast<const cx<double>*>(A.gamma64.p);
   a.binv = static_cast<const cx<double>*>(A.binv64.p);
-  a.lds_line = int(std::max<int64_t>(lds_elems_for(A.n), 3 * A.m));
+  a.lds_line = int(std::max<int64_t>(lds_elems_for<xch_t<T>>(A.n), 3 * A.m));
   // y-strip, used by the row pass to decide which rows take both half-steps
   a.j0y = p.prob.ndim == 2 ? int(p.ax[1].j0) : 0;
   a.my = p.prob.ndim == 2 ? int(p.ax[1].m) : 0;
@@ -856,14 +881,17 @@ sofft_status launch_pass(Plan& p, const PassRequest& rq, hipStream_t s) {
 
 sofft_status pass_residency(const Plan& p, bool row, int threads, int* blocks_per_cu, int* block_threads_out) {
   const Axis& A = p.ax[row ? 0 : 1];
-  const int lds_line = int(std::max<int64_t>(lds_elems_for(A.n), 3 * A.m));
+  const int lds_line = p.prob.dtype == SOFFT_C128 ? int(std::max<int64_t>(lds_elems_for<xch_t<double>>(A.n), 3 * A.m))
+                                                 : int(std::max<int64_t>(lds_elems_for<xch_t<float>>(A.n), 3 * A.m));
   return p.prob.dtype == SOFFT_C128 ? occupancy_n<double>(row, int(A.n), lds_line, threads, blocks_per_cu, block_threads_out)
                                     : occupancy_n<float>(row, int(A.n), lds_line, threads, blocks_per_cu, block_threads_out);
 }
 
 template <typename T, int N>
-static sofft_status tdse1d(Plan& p, const PassArgs<T>& a, int64_t nsteps, hipStream_t s) {
+static sofft_status tdse1d(Plan& p, PassArgs<T> a, int64_t nsteps, hipStream_t s) {
   constexpr int TPL = N / Shape<N>::P;
+  // one exchange buffer (fft), beside the twiddles
+  a.lds_line = int(std::max<int64_t>(fft_lds_elems<N>(), 3 * p.ax[0].m));
   const size_t lds = size_t(N) * sizeof(cx<double>) + size_t(a.lds_line) * sizeof(cx<xch_t<T>>);
   if (lds > kLdsBudget) {
     set_error("ECS strip too long for the LDS budget");
