@@ -85,6 +85,25 @@ def gpu_tdse(sofft, wl, torch, dtype, steps, warmup, seed=1):
     return dict(wall=wall, event_s=ev_s, kernels=kern, psi=result, npts=c.n * c.n)
 
 
+def gpu_tdse1d(sofft, wl, torch):
+    """The 1D workload: 4096 points, 4000 steps in one workgroup (state in LDS/registers)."""
+    c = wl.TDSE_1D
+    plan = sofft.Plan(c.n, c.L, R0=c.R0, theta=c.theta, charge=c.charge, a2=c.a2)
+    psi0 = torch.from_numpy(wl.gaussian_1d(plan.nodes(0))).cuda()
+    f = torch.from_numpy(c.pulse.at_midpoints(0.0, c.dt, c.nsteps)).cuda()
+    psi = psi0.clone()
+    plan.propagate(psi, c.dt, 50, f[:50])     # warm-up
+    psi.copy_(psi0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.propagate(psi, c.dt, c.nsteps, f)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.close()
+    return {"workload": f"1D n={c.n} c128, {c.nsteps} steps", "time_s": wall, "steps_per_s": c.nsteps / wall,
+            "value": c.n * c.nsteps / wall, "unit": "grid-point-steps/s", "us_per_step": wall / c.nsteps * 1e6}
+
+
 def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0):
     """Batched COCG to 1e-8 on the 512^2 stationary workload (Sec. III)."""
     c = wl.SSE_2D
@@ -241,6 +260,7 @@ def main():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--pcg-energies", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-1d", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -303,6 +323,13 @@ def main():
                 "rel_l2_vs_fp64_path": err, "steps": args.steps + args.warmup}
         log(f"  c64: {fp32['ms_per_step'] * 1e3:.1f} us/step, rel L2 vs FP64 path {err:.2e}")
 
+    tdse1d = None
+    if not args.no_1d:
+        log("TDSE 1D 4096 x 4000 steps")
+        tdse1d = gpu_tdse1d(sofft, wl, torch)
+        log(f"  {tdse1d['time_s'] * 1e3:.1f} ms, {tdse1d['steps_per_s']:.0f} steps/s "
+            f"({tdse1d['us_per_step']:.1f} us/step)")
+
     pcg = None
     if not args.no_pcg:
         log("SSE 512^2 batched COCG to 1e-8")
@@ -352,6 +379,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp32": fp32,
+        "tdse_1d": tdse1d,
         "pcg": pcg,
         "batch": batch,
         "learned": learned,

@@ -78,7 +78,7 @@ struct Plan {
   std::vector<double> host_partials;
   Timing timing;
   DevBuf sse_ws, sse_E;   // stationary-solver workspace and energies
-  // 2D: exp(-i V0 dt/2) on the grid for the dt in vphase_ht = dt/2 (NaN: none)
+  // exp(-i V0 dt/2) on the grid for the dt in vphase_ht = dt/2 (NaN: none)
   DevBuf vphase;
   double vphase_ht = __builtin_nan("");
 };
@@ -124,7 +124,7 @@ sofft_status launch_propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, 
                                  hipStream_t s);
 sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s);
 sofft_status launch_pass(Plan& p, const PassRequest& rq, hipStream_t s);
-// Build or refresh the potential-phase table of a 2D plan for dt (enqueued on s).
+// Build or refresh the potential-phase table of a plan for dt (enqueued on s).
 sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed);
 sofft_status pass_residency(const Plan& p, bool row, int threads, int* blocks_per_cu, int* block_threads);
 // *counter += delta by one device thread (graph-safe step offsets).

@@ -53,7 +53,7 @@ struct PassArgs {
   const double* x;        // x nodes
   const cx<double>* zx;   // z(x_j)
   const cx<double>* zy;   // z(y_j) (2D) or null
-  const cx<double>* vph;  // 2D: exp(-i V0(z_x, z_y) dt/2) on the grid, [ny][nx]; null when V0 = 0
+  const cx<double>* vph;  // exp(-i V0(z) dt/2) on the grid, [ny][nx] (1D: [nx]); null when V0 = 0
   int j0, m, levels;      // ECS strip of the pass axis
   int j0y, my;            // ECS strip of the y axis (row pass of a 2D grid)
   const cx<double>* alpha;
@@ -501,41 +501,43 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
   run_tiles<PERSIST>(a.ntiles, body);
 }
 
-// 1D: the whole propagation in one workgroup; psi stays in registers.
+// 1D: the whole propagation in one workgroup; psi stays in registers.  LDS
+// holds two exchange buffers (fft2); twiddles are read through the vector L1.
+// The static potential phase exp(-i V0 dt/2) comes from the plan's table (or is
+// 1 without a potential) and is multiplied by exp(-i f x dt/2) each step.
 template <typename T, int N>
 __global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const cx<double>* kin_half,
                                                              const cx<double>* kin_full, int64_t nsteps) {
   using X = xch_t<T>;
   constexpr int P = Shape<N>::P, TPL = N / P;
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<double>* tw = reinterpret_cast<cx<double>*>(smem);   // [twiddles: N][line]
+  cx<X>* lds = reinterpret_cast<cx<X>*>(smem);   // [line (lds_line)][second exchange buffer (N)]
   const int t = threadIdx.x;
-  const LineLDS<X> L{reinterpret_cast<cx<X>*>(tw + N), 0, 1};
+  const LineLDS<X> L{lds, 0, 1};
+  const LineLDS<X> Lb{lds, a.lds_line, 1};
   cx<double> v[P];
   cx<double> kf[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = widen(a.psi[t + TPL * s]);
 #pragma unroll
   for (int s = 0; s < P; ++s) kf[s] = kin_half[t + TPL * s];
-  stage_twiddles<N>(tw, a.tw);
-  __syncthreads();
-  fft<X, N, -1>(v, L, t, tw);
+  fft2<X, N, -1>(v, L, Lb, t, a.tw);
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kf[s]);
-  fft<X, N, +1>(v, L, t, tw);
+  fft2<X, N, +1>(v, L, Lb, t, a.tw);
   for (int64_t n = 0; n < nsteps; ++n) {
-    const double f = a.f_mid ? a.f_mid[n] : 0.0;
+    const double fh = (a.f_mid ? a.f_mid[n] : 0.0) * a.ht;
     pot_cn_pot<T, N>(v, L, t, a, [&](int e) {
-      const cx<double> z = a.zx[e];
-      return potential_phase(cmul(z, z) + cx<double>{a.a2, 0.0}, a.charge, f * a.x[e], a.ht);
+      const cx<double> ph = expi(fh * a.x[e], 0.0);
+      return a.vph ? cmul(a.vph[e], ph) : ph;
     });
     const cx<double>* kin = n + 1 == nsteps ? kin_half : kin_full;
 #pragma unroll
     for (int s = 0; s < P; ++s) kf[s] = kin[t + TPL * s];
-    fft<X, N, -1>(v, L, t, tw);
+    fft2<X, N, -1>(v, L, Lb, t, a.tw);
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kf[s]);
-    fft<X, N, +1>(v, L, t, tw);
+    fft2<X, N, +1>(v, L, Lb, t, a.tw);
   }
 #pragma unroll
   for (int s = 0; s < P; ++s) a.psi[t + TPL * s] = narrow<T>(v[s]);
@@ -547,7 +549,8 @@ __global__ void __launch_bounds__(256) k_vphase(cx<double>* out, int nx, int ny,
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= size_t(nx) * ny) return;
   const int jx = int(i % nx), jy = int(i / nx);
-  out[i] = potential_phase(cmul(zx[jx], zx[jx]) + cmul(zy[jy], zy[jy]) + cx<double>{a2, 0.0}, charge, 0.0, ht);
+  const cx<double> zy2 = zy ? cmul(zy[jy], zy[jy]) : cx<double>{0.0, 0.0};   // 1D: no y term
+  out[i] = potential_phase(cmul(zx[jx], zx[jx]) + zy2 + cx<double>{a2, 0.0}, charge, 0.0, ht);
 }
 
 __global__ void k_step_add(int64_t* counter, int64_t delta, int set) {
@@ -796,11 +799,11 @@ static sofft_status occupancy_n(bool row, int n, int lds_line, int threads, int*
   return SOFFT_EUNSUPPORTED;
 }
 
-// The table of exp(-i V0 dt/2) for this dt (2D plans with a potential).
+// The table of exp(-i V0 dt/2) for this dt (plans with a potential).
 sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
   if (changed) *changed = false;
-  if (p.prob.ndim != 2 || p.prob.charge == 0.0 || p.vphase_ht == 0.5 * dt) return SOFFT_OK;
-  const int nx = int(p.ax[0].n), ny = int(p.ax[1].n);
+  if (p.prob.charge == 0.0 || p.vphase_ht == 0.5 * dt) return SOFFT_OK;
+  const int nx = int(p.ax[0].n), ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
   const size_t bytes = size_t(nx) * ny * sizeof(cx<double>);
   if (!p.vphase.p) {
     if (hipMalloc(&p.vphase.p, bytes) != hipSuccess) {
@@ -813,7 +816,8 @@ sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
   const size_t n = size_t(nx) * ny;
   k_vphase<<<unsigned((n + 255) / 256), 256, 0, s>>>(static_cast<cx<double>*>(p.vphase.p), nx, ny,
                                                      static_cast<const cx<double>*>(p.ax[0].z_dev.p),
-                                                     static_cast<const cx<double>*>(p.ax[1].z_dev.p),
+                                                     p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p)
+                                                                      : nullptr,
                                                      p.prob.charge, p.prob.a2, 0.5 * dt);
   SOFFT_HIP_TRY(hipGetLastError());
   p.vphase_ht = 0.5 * dt;
@@ -890,9 +894,9 @@ sofft_status pass_residency(const Plan& p, bool row, int threads, int* blocks_pe
 template <typename T, int N>
 static sofft_status tdse1d(Plan& p, PassArgs<T> a, int64_t nsteps, hipStream_t s) {
   constexpr int TPL = N / Shape<N>::P;
-  // one exchange buffer (fft), beside the twiddles
+  // the line (with room for the CN strip) and a second exchange buffer
   a.lds_line = int(std::max<int64_t>(fft_lds_elems<N>(), 3 * p.ax[0].m));
-  const size_t lds = size_t(N) * sizeof(cx<double>) + size_t(a.lds_line) * sizeof(cx<xch_t<T>>);
+  const size_t lds = (size_t(a.lds_line) + fft_lds_elems<N>()) * sizeof(cx<xch_t<T>>);
   if (lds > kLdsBudget) {
     set_error("ECS strip too long for the LDS budget");
     return SOFFT_EUNSUPPORTED;
@@ -910,6 +914,8 @@ static sofft_status tdse1d(Plan& p, PassArgs<T> a, int64_t nsteps, hipStream_t s
 template <typename T>
 static sofft_status propagate_1d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
                                  hipStream_t s) {
+  sofft_status st0 = ensure_vphase(p, dt, s, nullptr);
+  if (st0 != SOFFT_OK) return st0;
   PassArgs<T> a = axis_args<T>(p, 0, psi, dt);
   a.f_mid = f_mid;
   switch (p.ax[0].n) {

@@ -132,3 +132,14 @@ def test_flexible_cocg_falls_back_on_a_useless_preconditioner():
     x, it, res, fb = lo.flexible_cocg(op, f, noise, rtol=1e-9, patience=10, maxit=5000)
     assert fb
     assert res <= 1e-9
+
+
+def test_library_initial_weights_follow_the_oracle_recipe():
+    # the package's seeded initial weights (input generation) and the oracle's
+    # initialisation draw the same numbers in the library's parameter order
+    from paper_1505_06707_amd.lp_data import flat_params, init_weights, unflat_params
+    w = init_weights(7)
+    assert np.array_equal(w, flat_params(lo.init_params(7)))
+    back = unflat_params(w)
+    for (W, b), (W0, b0) in zip(back, lo.init_params(7)):
+        assert np.allclose(W, W0, rtol=1e-7) and np.array_equal(b, b0)
