@@ -158,8 +158,9 @@ __device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const L
 
 // Blocks of the 2D passes have 1024 threads (four 1024-point lines, or more
 // shorter ones) for P = 4 shapes, which then keep <= 128 VGPRs (4 waves per
-// SIMD), and 512 threads for P = 12 shapes (radix 3), which need more
-// registers and run 2 waves per SIMD.
+// SIMD), and at most 512 threads for P = 12 shapes (radix 3), which need more
+// registers: 168 VGPRs at 3 waves per SIMD (a few spills, measured faster
+// for batches of such lines than 2 waves without spills).
 #ifndef SOFFT_ROW_THREADS
 #define SOFFT_ROW_THREADS 1024
 #endif
@@ -169,7 +170,7 @@ __device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const L
 constexpr int kRowThreads = SOFFT_ROW_THREADS;
 constexpr int kColThreads = SOFFT_COL_THREADS;
 #ifndef SOFFT_MIN_WAVES_WIDE
-#define SOFFT_MIN_WAVES_WIDE 2
+#define SOFFT_MIN_WAVES_WIDE 3
 #endif
 template <int N>
 constexpr int min_waves_per_simd() {
@@ -343,35 +344,50 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     cx<double> v[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = live ? widen(line[t + TPL * s]) : cx<double>{0.0, 0.0};
+    // kinetic factors, static potential phases and x of the field term: with
+    // P = 4 fetched before the transforms (latency hidden behind them); the
+    // P = 12 shapes fetch them where they are used, which keeps 120 VGPRs
+    // free during the transforms.
+    constexpr bool early = P == 4;
     cx<double> kin[P];
+    auto load_kin = [&]() {
 #pragma unroll
-    for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
-    // static potential phase and x of the field term, fetched before the transforms
+      for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
+    };
     cx<double> vps[P];
     double xs[P];
     double f = 0.0;
-    if (a.do_pot) {
-      const cx<double>* vrow = a.vph ? a.vph + size_t(crow) * N : nullptr;
+    auto load_pot = [&]() {
+      if (a.do_pot) {
+        const cx<double>* vrow = a.vph ? a.vph + size_t(crow) * N : nullptr;
 #pragma unroll
-      for (int s = 0; s < P; ++s) {
-        vps[s] = vrow ? vrow[t + TPL * s] : cx<double>{1.0, 0.0};
-        xs[s] = a.x[t + TPL * s];
+        for (int s = 0; s < P; ++s) {
+          vps[s] = vrow ? vrow[t + TPL * s] : cx<double>{1.0, 0.0};
+          xs[s] = a.x[t + TPL * s];
+        }
+        const double* fm = run_field(a, run);
+        f = fm ? fm[step] : 0.0;
       }
-      const double* fm = run_field(a, run);
-      f = fm ? fm[step] : 0.0;
+    };
+    if constexpr (early) {
+      load_kin();
+      load_pot();
     }
     if constexpr (fft_buffers<N, X>() == 2) {
       const LineLDS<X> Lb{lines, l * a.lds_line + fft_lds_elems<N>(), 1};
       fft2<X, N, -1>(v, L, Lb, t, a.tw);
+      if constexpr (!early) load_kin();
 #pragma unroll
       for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
       fft2<X, N, +1>(v, L, Lb, t, a.tw);
     } else {
       fft<X, N, -1>(v, L, t, a.tw);
+      if constexpr (!early) load_kin();
 #pragma unroll
       for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
       fft<X, N, +1>(v, L, t, a.tw);
     }
+    if constexpr (!early) load_pot();
     if (a.do_pot) {
       // Rows outside the y-strip get both potential half-steps here (C_y is the
       // identity on them); rows on it get the first, the column pass the second.
