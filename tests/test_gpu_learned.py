@@ -143,3 +143,33 @@ def test_training_and_flexible_solve():
         assert res <= 1e-8 * (1 + 1e-3)
     lp.close()
     plan.close()
+
+
+def test_full_learned_workload_sampled():
+    """The learned workload at full size (1024^2, 64 energies) in the
+    configuration the benchmark uses: every energy meets 1e-8 (directly or
+    through the fallback), checked by the oracle's true residual on samples."""
+    s = _sofft()
+    c = wl.LEARNED_2D
+    plan = s.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=c.theta, charge=c.charge, a2=c.a2)
+    src = [torch.from_numpy(-wl.smooth_source(c.n, c.n, seed=sd)).cuda() for sd in (1001,)]
+    r, e, Es, iters = make_pairs(plan, src, [0.5, 1.5], schedule=(2, 8, 32))
+    print(f"pairs {r.shape[0]} from {iters} plain iterations", flush=True)
+    lp = s.LearnedCorrection()
+    from paper_1505_06707_amd.lp_data import init_weights
+    lp.set_weights(init_weights(7))
+    losses = lp.train(plan, r, e, Es, epochs=3, batch=2, lr=2e-3, seed=11)
+    assert np.all(np.isfinite(losses))
+    del r, e
+    f = torch.from_numpy(-wl.smooth_source(c.n, c.n, seed=0)).cuda()
+    E = c.energies()
+    x, st, code = plan.sse_solve_learned(lp, f, E, rtol=c.rtol, patience=30)
+    assert code == 0 and all(q["status"] == 0 for q in st)
+    fh = f.cpu().numpy()
+    for k in (0, len(E) - 1):
+        res = _oracle_true_residual(c.n, E[k], fh, x[k].cpu().numpy())
+        print(f"   E={E[k]:.3f}: {st[k]['iterations']} iterations (fell back: {st[k]['fell_back']}), "
+              f"oracle true residual {res:.2e}", flush=True)
+        assert res <= c.rtol * (1 + 1e-3)
+    lp.close()
+    plan.close()
