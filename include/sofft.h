@@ -147,6 +147,42 @@ sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_ener
 sofft_status sofft_sse_apply(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double field,
                              void* stream);
 
+/* sofft_sse_solve with a shifted divisor in the FFT preconditioner of
+ * Eq. PreconFFT: P^-1 = F^-1 (K - E_j - i eta_j)^-1 F for energy j.  This is
+ * not the paper's preconditioner (eta = 0 is).  The symbol stays even in k, so
+ * P^-1 stays complex symmetric and the COCG recurrences of sofft_sse_solve
+ * apply unchanged; the solution x_j of Eq. linsys is the same, only the
+ * iteration count changes.
+ *   eta_host  host, nE shifts, finite and >= 0 (an entry of 0 gives exactly the
+ *             arithmetic of sofft_sse_solve for that energy)
+ * Other arguments, workspace, blocking and status: as sofft_sse_solve;
+ * SOFFT_EINVAL for a negative or non-finite shift. */
+sofft_status sofft_sse_solve_shifted(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
+                                     const double* eta_host, int32_t nE, double field, void* x_out, double rtol,
+                                     int32_t maxit, sofft_solve_stats* stats, void* stream);
+
+/* sofft_sse_apply with the shifted divisor (op 1: w = F^-1 (K - E - i eta)^-1 F v;
+ * op 0 ignores eta).  eta finite and >= 0, else SOFFT_EINVAL.  Asynchronous. */
+sofft_status sofft_sse_apply_shifted(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double eta,
+                                     double field, void* stream);
+
+/* Choose a divisor shift per energy for sofft_sse_solve_shifted by short
+ * solves of the problem itself: all nE * ncand (energy, candidate) systems
+ * run as one batched COCG limited to probe_iters iterations.  A candidate
+ * that reaches rtol ranks by its iterations, the others after it by the
+ * residual they reached, breakdowns last; ties keep the earlier candidate.
+ *   f               device, [n_y][n_x], one right-hand side for all energies
+ *   E_host          host, nE energies (finite)
+ *   eta_candidates  host, ncand shifts, finite and >= 0
+ *   scratch_x       device, nE * ncand * n_x * n_y complex128, overwritten
+ *   eta_out         host, nE entries, written with the chosen candidates
+ * The plan's solver workspace grows to nE * ncand systems (kept until
+ * sofft_plan_destroy).  Blocking.  SOFFT_OK unless an argument is bad
+ * (SOFFT_EINVAL) or a launch or allocation fails. */
+sofft_status sofft_sse_tune_shift(sofft_plan* plan, const void* f, const double* E_host, int32_t nE, double field,
+                                  const double* eta_candidates, int32_t ncand, int32_t probe_iters, double rtol,
+                                  void* scratch_x, double* eta_out, void* stream);
+
 /* ------------------------------------------------------------------ batches
  * Many independent 2D propagations of uneven size advanced together (the
  * step of Sec. II, as in sofft_propagate, applied to every run).  Runs with an

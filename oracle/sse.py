@@ -14,7 +14,10 @@ Readings:
   f - A x and restart from it while it still exceeds rtol.
 * 2D: K = (k_x^2 + k_y^2)/2 and C = C_x (x) I + I (x) C_y as in the TDSE;
   U = V0(z_x, z_y) + f x with the field value f (zero once the pulse is over).
-* The preconditioner's divisor k^2/2 - E is used as printed.
+* The preconditioner's divisor k^2/2 - E is used as printed.  The optional
+  shift eta (divisor k^2/2 - E - i eta) is not from the paper; eta = 0 is the
+  printed form.  The shifted symbol is still even in k, so P^-1 stays
+  complex symmetric and COCG still applies.
 """
 import numpy as np
 
@@ -25,11 +28,13 @@ class Operator:
     """A = F^-1 K F + C + U - E (Sec. III, Eq. linsys) for a 1D or 2D problem
     built from ``oracle.tdse`` axes, and the FFT preconditioner."""
 
-    def __init__(self, axes, V, E):
-        # axes: (ax,) in 1D or (ax, ay) in 2D; V: static potential on the grid.
+    def __init__(self, axes, V, E, eta=0.0):
+        # axes: (ax,) in 1D or (ax, ay) in 2D; V: static potential on the grid;
+        # eta: shift of the preconditioner's divisor (0: as printed).
         self.axes = axes
         self.V = np.asarray(V, dtype=complex)
         self.E = complex(E)
+        self.eta = float(eta)
         if len(axes) == 1:
             self.K = axes[0].k ** 2 / 2
         else:
@@ -60,8 +65,11 @@ class Operator:
         return self._Finv(self.K * self._F(v)) + self._C(v) + (self.V - self.E) * v
 
     def precond(self, r):
-        """P^-1 r = F^-1 (K - E)^-1 F r (Sec. III, Eq. PreconFFT)."""
-        return self._Finv(self._F(r) / (self.K - self.E))
+        """P^-1 r = F^-1 (K - E)^-1 F r (Sec. III, Eq. PreconFFT); with a shift,
+        F^-1 (K - E - i eta)^-1 F r."""
+        if self.eta == 0.0:
+            return self._Finv(self._F(r) / (self.K - self.E))
+        return self._Finv(self._F(r) / (self.K - self.E - 1j * self.eta))
 
     def dense(self):
         """A as a dense matrix, column by column (tiny grids only)."""

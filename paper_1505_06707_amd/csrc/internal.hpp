@@ -77,7 +77,7 @@ struct Plan {
   DevBuf partials;   // reduction scratch (norms)
   std::vector<double> host_partials;
   Timing timing;
-  DevBuf sse_ws, sse_E;   // stationary-solver workspace and energies
+  DevBuf sse_ws, sse_E, sse_eta;   // stationary-solver workspace, energies, divisor shifts
   // exp(-i V0 dt/2) on the grid for the dt in vphase_ht = dt/2 (NaN: none)
   DevBuf vphase;
   double vphase_ht = __builtin_nan("");
@@ -141,9 +141,15 @@ sofft_status lp_apply(LpNet& net, const cx<double>* r, cx<double>* z, int B, int
 
 // Stationary solver (sse.hip).  lp = null: plain FFT preconditioner (COCG);
 // otherwise flexible COCG with the learned correction and the fallback.
+// eta_host (nE shifts, may be null): divisor K - E - i eta of the
+// preconditioner per energy.
 sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E_host, int nE, double field,
                        void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s,
-                       LpNet* lp = nullptr, int patience = 0);
-sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s);
+                       LpNet* lp = nullptr, int patience = 0, const double* eta_host = nullptr);
+sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s,
+                       double eta = 0.0);
+sofft_status sse_tune_shift(Plan& p, const void* f, const double* E_host, int nE, double field,
+                            const double* cand, int ncand, int probe_iters, double rtol, void* scratch_x,
+                            double* eta_out, hipStream_t s);
 
 }  // namespace sofft

@@ -366,6 +366,7 @@ sofft_status sofft_plan_destroy(sofft_plan* plan) {
   dev_free(plan->partials);
   dev_free(plan->sse_ws);
   dev_free(plan->sse_E);
+  dev_free(plan->sse_eta);
   dev_free(plan->vphase);
   delete plan;
   return SOFFT_OK;
@@ -428,6 +429,64 @@ sofft_status sofft_sse_apply(sofft_plan* plan, int32_t op, const void* v, void* 
     return SOFFT_EINVAL;
   }
   return sse_apply(*plan, op, v, w, E, field, reinterpret_cast<hipStream_t>(stream));
+}
+
+static bool shifts_ok(const double* eta, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(eta[i]) || eta[i] < 0.0) return false;
+  return true;
+}
+
+sofft_status sofft_sse_solve_shifted(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
+                                     const double* eta_host, int32_t nE, double field, void* x_out, double rtol,
+                                     int32_t maxit, sofft_solve_stats* stats, void* stream) {
+  if (!plan || !f || !E_host || !eta_host || nE <= 0 || !x_out || !(rtol > 0) || maxit <= 0 ||
+      !std::isfinite(field)) {
+    set_error("bad argument to sofft_sse_solve_shifted");
+    return SOFFT_EINVAL;
+  }
+  for (int e = 0; e < nE; ++e)
+    if (!std::isfinite(E_host[e])) {
+      set_error("energies must be finite");
+      return SOFFT_EINVAL;
+    }
+  if (!shifts_ok(eta_host, nE)) {
+    set_error("shifts must be finite and >= 0");
+    return SOFFT_EINVAL;
+  }
+  return sse_solve(*plan, f, f_per_energy, E_host, nE, field, x_out, rtol, maxit, stats,
+                   reinterpret_cast<hipStream_t>(stream), nullptr, 0, eta_host);
+}
+
+sofft_status sofft_sse_apply_shifted(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double eta,
+                                     double field, void* stream) {
+  if (!plan || !v || !w || (op != 0 && op != 1) || !std::isfinite(E) || !std::isfinite(field) ||
+      !shifts_ok(&eta, 1)) {
+    set_error("bad argument to sofft_sse_apply_shifted");
+    return SOFFT_EINVAL;
+  }
+  return sse_apply(*plan, op, v, w, E, field, reinterpret_cast<hipStream_t>(stream), eta);
+}
+
+sofft_status sofft_sse_tune_shift(sofft_plan* plan, const void* f, const double* E_host, int32_t nE, double field,
+                                  const double* eta_candidates, int32_t ncand, int32_t probe_iters, double rtol,
+                                  void* scratch_x, double* eta_out, void* stream) {
+  if (!plan || !f || !E_host || nE <= 0 || !eta_candidates || ncand <= 0 || probe_iters <= 0 ||
+      !(rtol > 0) || !scratch_x || !eta_out || !std::isfinite(field)) {
+    set_error("bad argument to sofft_sse_tune_shift");
+    return SOFFT_EINVAL;
+  }
+  for (int e = 0; e < nE; ++e)
+    if (!std::isfinite(E_host[e])) {
+      set_error("energies must be finite");
+      return SOFFT_EINVAL;
+    }
+  if (!shifts_ok(eta_candidates, ncand)) {
+    set_error("shift candidates must be finite and >= 0");
+    return SOFFT_EINVAL;
+  }
+  return sse_tune_shift(*plan, f, E_host, nE, field, eta_candidates, ncand, probe_iters, rtol, scratch_x, eta_out,
+                        reinterpret_cast<hipStream_t>(stream));
 }
 
 sofft_status sofft_norm2(sofft_plan* plan, const void* psi, double* norm2_host, void* stream) {

@@ -22,6 +22,8 @@
 // so results do not depend on scheduling.
 #include <algorithm>
 #include <cmath>
+#include <utility>
+#include <vector>
 
 #include "line_fft.hpp"
 #include "potential.hpp"
@@ -59,6 +61,7 @@ struct SseArgs {
   int f_per_energy;
   const cx<double>* V;         // U on the grid, [n_y][n_x]
   const double* E;             // [nE]
+  const double* eta;           // [nE] shift of the preconditioner's divisor (K - E - i eta), or null
   CocgScalars* sc;             // [nE]
   double* part_rr;             // [nE][nblk_row]
   cx<double>* part_rz;         // [nE][nblk_row]
@@ -309,12 +312,25 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_col_prec(SseArgs a, int wan
   for (int s = 0; s < P; ++s) v[s] = live ? a.s[base + size_t(t + TPL * s) * ld] : cx<double>{0.0, 0.0};
   fft<double, N, -1>(v, L, t, a.twy);
   const double kx = kval(ccol, a.nx, a.Lx), E = a.E[e];
+  const double eta = a.eta ? a.eta[e] : 0.0;
   const double scale = 1.0 / (double(a.nx) * double(N));
+  if (eta == 0.0) {   // uniform over the block
 #pragma unroll
-  for (int s = 0; s < P; ++s) {
-    const double ky = kval(t + TPL * s, N, a.Ly);
-    const double d = 0.5 * (kx * kx + ky * ky) - E;   // (K - E), as printed in Eq. PreconFFT
-    v[s] = (scale / d) * v[s];
+    for (int s = 0; s < P; ++s) {
+      const double ky = kval(t + TPL * s, N, a.Ly);
+      const double d = 0.5 * (kx * kx + ky * ky) - E;   // (K - E), as printed in Eq. PreconFFT
+      v[s] = (scale / d) * v[s];
+    }
+  } else {
+    // Shifted divisor K - E - i eta: the symbol stays even in k, so P^-1 stays
+    // complex symmetric and COCG applies unchanged.
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const double ky = kval(t + TPL * s, N, a.Ly);
+      const double d = 0.5 * (kx * kx + ky * ky) - E;
+      const double q = scale / (d * d + eta * eta);   // 1/(d - i eta) = (d + i eta)/(d^2 + eta^2)
+      v[s] = cmul(v[s], cx<double>{q * d, q * eta});
+    }
   }
   fft<double, N, +1>(v, L, t, a.twy);
   if (live) {
@@ -710,9 +726,24 @@ static sofft_status sse_check_plan(const Plan& p) {
   return SOFFT_OK;
 }
 
+// Copy n doubles from the host into a plan-owned device buffer (grown as needed).
+static sofft_status upload_doubles(DevBuf& b, const double* host, int n, hipStream_t s) {
+  if (!b.p || b.bytes < sizeof(double) * n) {
+    dev_free(b);
+    if (hipMalloc(&b.p, sizeof(double) * n) != hipSuccess) {
+      b.p = nullptr;
+      set_error("hipMalloc failed");
+      return SOFFT_ENOMEM;
+    }
+    b.bytes = sizeof(double) * n;
+  }
+  SOFFT_HIP_TRY(hipMemcpyAsync(b.p, host, sizeof(double) * n, hipMemcpyHostToDevice, s));
+  return SOFFT_OK;
+}
+
 sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E_host, int nE, double field,
                        void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s, LpNet* lp,
-                       int patience) {
+                       int patience, const double* eta_host) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
   SseArgs a{};
@@ -734,6 +765,10 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
   }
   SOFFT_HIP_TRY(hipMemcpyAsync(p.sse_E.p, E_host, sizeof(double) * nE, hipMemcpyHostToDevice, s));
   a.E = static_cast<const double*>(p.sse_E.p);
+  if (eta_host) {
+    if ((st = upload_doubles(p.sse_eta, eta_host, nE, s)) != SOFFT_OK) return st;
+    a.eta = static_cast<const double*>(p.sse_eta.p);
+  }
   SseLauncher L = sse_launcher(p.ax[0].n, p.ax[1].n);
   Timing& tm = p.timing;
   const int sb = (nE + 63) / 64;
@@ -819,8 +854,43 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
   return worst;
 }
 
+// Choose, per energy, the shift of the preconditioner's divisor from a set of
+// candidates by short solves of the problem itself: every (energy, candidate)
+// pair is one system of a batched solve limited to probe_iters iterations; a
+// candidate that converges ranks by its iterations, the others after it by
+// the residual they reached; breakdowns rank last; ties keep the earlier
+// candidate.
+sofft_status sse_tune_shift(Plan& p, const void* f, const double* E_host, int nE, double field,
+                            const double* cand, int ncand, int probe_iters, double rtol, void* scratch_x,
+                            double* eta_out, hipStream_t s) {
+  const int n = nE * ncand;
+  std::vector<double> Ex(n), ex(n);
+  for (int e = 0; e < nE; ++e)
+    for (int c = 0; c < ncand; ++c) {
+      Ex[size_t(e) * ncand + c] = E_host[e];
+      ex[size_t(e) * ncand + c] = cand[c];
+    }
+  std::vector<sofft_solve_stats> st(n);
+  const sofft_status r = sse_solve(p, f, 0, Ex.data(), n, field, scratch_x, rtol, probe_iters, st.data(), s,
+                                   nullptr, 0, ex.data());
+  if (r != SOFFT_OK && r != SOFFT_NOT_CONVERGED && r != SOFFT_BREAKDOWN) return r;
+  for (int e = 0; e < nE; ++e) {
+    int best = 0;
+    auto key = [&](int c) {
+      const sofft_solve_stats& q = st[size_t(e) * ncand + c];
+      if (q.status == SOFFT_OK) return std::make_pair(0, double(q.iterations));
+      if (q.status == SOFFT_NOT_CONVERGED) return std::make_pair(1, q.rel_residual);
+      return std::make_pair(2, 0.0);
+    };
+    for (int c = 1; c < ncand; ++c)
+      if (key(c) < key(best)) best = c;
+    eta_out[e] = cand[best];
+  }
+  return SOFFT_OK;
+}
+
 // w = A v (op 0) or w = P^-1 v (op 1) for one energy.
-sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s) {
+sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s, double eta) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
   SseArgs a{};
@@ -836,6 +906,10 @@ sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double
   }
   SOFFT_HIP_TRY(hipMemcpyAsync(p.sse_E.p, &E, sizeof(double), hipMemcpyHostToDevice, s));
   a.E = static_cast<const double*>(p.sse_E.p);
+  if (eta != 0.0) {
+    if ((st = upload_doubles(p.sse_eta, &eta, 1, s)) != SOFFT_OK) return st;
+    a.eta = static_cast<const double*>(p.sse_eta.p);
+  }
   CocgScalars c{};
   c.state = kActive;
   SOFFT_HIP_TRY(hipMemcpyAsync(a.sc, &c, sizeof(c), hipMemcpyHostToDevice, s));

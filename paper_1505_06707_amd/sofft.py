@@ -69,6 +69,14 @@ _SIGS = {
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_sse_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_void_p]),
+    "sofft_sse_solve_shifted": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                                               ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_sse_apply_shifted": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]),
+    "sofft_sse_tune_shift": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "sofft_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sofft_batch_propagate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
@@ -227,20 +235,27 @@ class Plan:
         _check(lib().sofft_timing_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
 
-    def sse_apply(self, op, v, E, field=0.0, out=None, stream=None):
-        """w = A v (op 0) or w = P^-1 v (op 1) at energy E (device tensors)."""
+    def sse_apply(self, op, v, E, field=0.0, out=None, stream=None, eta=0.0):
+        """w = A v (op 0) or w = P^-1 v (op 1) at energy E (device tensors);
+        eta != 0 shifts the preconditioner's divisor to K - E - i eta."""
         import torch
         ptr = _dev_ptr(v, torch.complex128, self.numel, "v")
         if out is None:
             out = torch.empty_like(v)
         optr = _dev_ptr(out, torch.complex128, self.numel, "out")
-        _check(lib().sofft_sse_apply(self._h, int(op), ptr, optr, float(E), float(field), _stream(stream)))
+        if eta:
+            _check(lib().sofft_sse_apply_shifted(self._h, int(op), ptr, optr, float(E), float(eta), float(field),
+                                                 _stream(stream)))
+        else:
+            _check(lib().sofft_sse_apply(self._h, int(op), ptr, optr, float(E), float(field), _stream(stream)))
         return out
 
-    def sse_solve(self, f, energies, field=0.0, rtol=1e-8, maxit=10000, out=None, stream=None):
+    def sse_solve(self, f, energies, field=0.0, rtol=1e-8, maxit=10000, out=None, stream=None, eta=None):
         """Solve (H - E_j) x_j = f for every energy; returns (x, stats, status).
 
-        f: complex128 device tensor [ny][nx] (shared) or [nE][ny][nx]."""
+        f: complex128 device tensor [ny][nx] (shared) or [nE][ny][nx].
+        eta: None (the preconditioner of Eq. PreconFFT) or per-energy shifts of
+        its divisor (sofft_sse_solve_shifted)."""
         import torch
         E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
         nE = len(E)
@@ -250,12 +265,35 @@ class Plan:
             out = torch.empty((nE,) + self.shape, dtype=torch.complex128, device=f.device)
         optr = _dev_ptr(out, torch.complex128, nE * self.numel, "out")
         stats = (SolveStats * nE)()
-        code = lib().sofft_sse_solve(self._h, fptr, per, E.ctypes.data_as(ctypes.c_void_p), nE, float(field),
-                                     optr, float(rtol), int(maxit), stats, _stream(stream))
+        if eta is None:
+            code = lib().sofft_sse_solve(self._h, fptr, per, E.ctypes.data_as(ctypes.c_void_p), nE, float(field),
+                                         optr, float(rtol), int(maxit), stats, _stream(stream))
+        else:
+            sh = np.ascontiguousarray(np.broadcast_to(np.asarray(eta, dtype=np.float64), (nE,)))
+            code = lib().sofft_sse_solve_shifted(self._h, fptr, per, E.ctypes.data_as(ctypes.c_void_p),
+                                                 sh.ctypes.data_as(ctypes.c_void_p), nE, float(field), optr,
+                                                 float(rtol), int(maxit), stats, _stream(stream))
         _check(code)
         rows = [dict(iterations=s.iterations, status=s.status, restarts=s.restarts,
                      rel_residual=s.rel_residual) for s in stats]
         return out, rows, code
+
+    def sse_tune_shift(self, f, energies, candidates, probe_iters=24, rtol=1e-8, field=0.0, stream=None):
+        """Per-energy divisor shift chosen from the candidates by short batched
+        solves (sofft_sse_tune_shift); f is one right-hand side [ny][nx]."""
+        import torch
+        E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
+        cand = np.ascontiguousarray(np.asarray(candidates, dtype=np.float64).ravel())
+        nE, nc = len(E), len(cand)
+        fptr = _dev_ptr(f, torch.complex128, self.numel, "f")
+        scratch = torch.empty((nE * nc,) + self.shape, dtype=torch.complex128, device=f.device)
+        sptr = _dev_ptr(scratch, torch.complex128, nE * nc * self.numel, "scratch")
+        out = np.zeros(nE, dtype=np.float64)
+        _check(lib().sofft_sse_tune_shift(self._h, fptr, E.ctypes.data_as(ctypes.c_void_p), nE, float(field),
+                                          cand.ctypes.data_as(ctypes.c_void_p), nc, int(probe_iters), float(rtol),
+                                          sptr, out.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        del scratch
+        return out
 
     def sse_solve_learned(self, lp, f, energies, field=0.0, rtol=1e-8, maxit=10000, patience=30, out=None,
                           stream=None):

@@ -96,3 +96,85 @@ def test_full_workload_true_residual():
         r = f - oop.matvec(xs[j])
         assert np.linalg.norm(r) / np.linalg.norm(f) <= c.rtol * (1 + 1e-3), j
     plan.close()
+
+
+# ---- shifted divisor K - E - i eta (an option outside the paper; eta = 0 is Eq. PreconFFT)
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (128, 96)])
+def test_shifted_preconditioner_matches_oracle(nx, ny):
+    print(f"shifted P^-1 {nx}x{ny}", flush=True)
+    plan, _, ax, ay = _setup(nx, ny, E=1.1)
+    V = ot.softcore(1.0, 0.64, ax.z[None, :], ay.z[:, None])
+    rng = np.random.default_rng(nx * 3 + ny)
+    v = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    for eta in (0.05, 0.3):
+        w = plan.sse_apply(1, torch.from_numpy(v).cuda(), 1.1, eta=eta)
+        torch.cuda.synchronize()
+        want = osse.Operator((ax, ay), V, 1.1, eta=eta).precond(v)
+        assert rel_l2(w.cpu().numpy(), want) < 1e-13
+    plan.close()
+
+
+def test_zero_shift_is_the_plain_solve_bit_for_bit():
+    plan, _, _, _ = _setup(64, 64)
+    f = torch.from_numpy(wl.smooth_source(64, 64, seed=9)).cuda()
+    Es = [0.3, 1.2]
+    x0, st0, _ = plan.sse_solve(f, Es, rtol=1e-10)
+    x1, st1, _ = plan.sse_solve(f, Es, rtol=1e-10, eta=[0.0, 0.0])
+    assert torch.equal(x0, x1)
+    assert [s["iterations"] for s in st0] == [s["iterations"] for s in st1]
+    plan.close()
+
+
+def test_shifted_solve_fewer_iterations_same_solution():
+    """128^2 with the soft-core potential and ECS: the shifted solve reaches the
+    oracle's true residual bound with fewer iterations than the plain one, and
+    its iteration count follows the oracle's shifted COCG."""
+    n = 128
+    plan, _, ax, ay = _setup(n, n)
+    V = ot.softcore(1.0, 0.64, ax.z[None, :], ay.z[:, None])
+    fh = -wl.smooth_source(n, n, seed=1001)
+    f = torch.from_numpy(fh).cuda()
+    Es = [0.7, 1.35, 2.0]
+    _, st0, c0 = plan.sse_solve(f, Es, rtol=1e-8)
+    x1, st1, c1 = plan.sse_solve(f, Es, rtol=1e-8, eta=0.1)
+    assert c0 == 0 and c1 == 0
+    for j, E in enumerate(Es):
+        op = osse.Operator((ax, ay), V, E, eta=0.1)
+        true = np.linalg.norm(fh - op.matvec(x1[j].cpu().numpy())) / np.linalg.norm(fh)
+        _, it_o, _ = osse.cocg(op, fh, rtol=1e-8)
+        print(f"   E={E}: plain {st0[j]['iterations']}, shifted {st1[j]['iterations']} "
+              f"(oracle {it_o}), oracle true residual {true:.2e}", flush=True)
+        assert true <= 1e-8 * (1 + 1e-3)
+        assert st1[j]["iterations"] < st0[j]["iterations"]
+        assert abs(st1[j]["iterations"] - it_o) <= max(2, it_o // 20)
+    plan.close()
+
+
+def test_tune_shift_picks_a_candidate_that_does_not_lose():
+    n = 128
+    plan, _, _, _ = _setup(n, n)
+    f = torch.from_numpy(-wl.smooth_source(n, n, seed=1001)).cuda()
+    Es = [0.05, 0.7, 2.0]
+    cand = [0.0, 0.05, 0.1, 0.2]
+    eta = plan.sse_tune_shift(f, Es, cand, probe_iters=16)
+    print(f"   tuned shifts {eta}", flush=True)
+    assert all(e in cand for e in eta)
+    _, st0, _ = plan.sse_solve(f, Es, rtol=1e-8)
+    _, st1, c1 = plan.sse_solve(f, Es, rtol=1e-8, eta=eta)
+    assert c1 == 0
+    assert sum(s["iterations"] for s in st1) <= sum(s["iterations"] for s in st0)
+    plan.close()
+
+
+def test_shift_arguments_are_checked():
+    from paper_1505_06707_amd import sofft
+    plan, _, _, _ = _setup(64, 64)
+    f = torch.from_numpy(wl.smooth_source(64, 64, seed=2)).cuda()
+    with pytest.raises(sofft.SofftError):
+        plan.sse_solve(f, [0.5], eta=[-0.1])
+    with pytest.raises(sofft.SofftError):
+        plan.sse_solve(f, [0.5], eta=[float("nan")])
+    with pytest.raises(sofft.SofftError):
+        plan.sse_tune_shift(f, [0.5], [0.1, -1.0])
+    plan.close()

@@ -339,3 +339,49 @@ def test_cocg_matches_dense_gaussian_elimination(dim):
     xd = sse.dense_solve(op, f)
     assert res <= 1e-13
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
+
+
+# The shifted divisor k^2/2 - E - i eta is an option outside the paper
+# (eta = 0 is Eq. PreconFFT as printed); these pin the oracle's version of it.
+def test_shifted_preconditioner_on_plane_waves():
+    """Closed form: a grid plane wave exp(i(k_x x + k_y y)) is an eigenvector of
+    the FFT preconditioner with eigenvalue 1/((k_x^2 + k_y^2)/2 - E - i eta)."""
+    ax, ay = _axis(32, 12.8, R0=4.0), _axis(16, 6.4, R0=2.0)
+    V = tdse.softcore(1.0, 0.64, ax.z[None, :], ay.z[:, None])
+    E, eta = 0.8, 0.15
+    op = sse.Operator((ax, ay), V, E, eta=eta)
+    X, Y = np.meshgrid(ax.x, ay.x)
+    for nx_, ny_ in ((0, 0), (3, 1), (-5, 2), (7, -6)):
+        kx, ky = 2 * np.pi * nx_ / ax.L, 2 * np.pi * ny_ / ay.L
+        v = np.exp(1j * (kx * X + ky * Y))
+        want = v / ((kx ** 2 + ky ** 2) / 2 - E - 1j * eta)
+        assert np.max(np.abs(op.precond(v) - want)) < 1e-12 * np.max(np.abs(want))
+
+
+def test_shifted_preconditioner_is_complex_symmetric():
+    ax, ay = _axis(8, 3.2, R0=1.0), _axis(6, 2.4, R0=0.8)
+    op = sse.Operator((ax, ay), np.zeros((6, 8)), 0.5, eta=0.3)
+    n = 48
+    P = np.empty((n, n), dtype=complex)
+    for j in range(n):
+        e = np.zeros(n, dtype=complex)
+        e[j] = 1.0
+        P[:, j] = op.precond(e.reshape(6, 8)).ravel()
+    assert np.allclose(P, P.T, atol=1e-14)
+    assert not np.allclose(P, P.conj().T, atol=1e-6)
+
+
+def test_shifted_cocg_reaches_the_dense_solution():
+    """The shift changes the iterations, not the solution of Eq. linsys."""
+    rng = np.random.default_rng(8)
+    ax, ay = _axis(16, 6.4, R0=2.0), _axis(16, 6.4, R0=2.0)
+    V = tdse.softcore(1.0, 0.64, ax.z[None, :], ay.z[:, None])
+    f = rng.normal(size=(16, 16)) + 1j * rng.normal(size=(16, 16))
+    xd = sse.dense_solve(sse.Operator((ax, ay), V, 0.6), f)
+    its = []
+    for eta in (0.0, 0.1, 0.4):
+        x, it, res = sse.cocg(sse.Operator((ax, ay), V, 0.6, eta=eta), f, rtol=1e-13)
+        assert res <= 1e-13
+        assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
+        its.append(it)
+    assert len(set(its)) > 1   # the shift is in effect
