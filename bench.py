@@ -124,6 +124,7 @@ def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0):
              "row_precond_dot": sofft.KERNEL_SSE_ROW_PREC}
     kern = {k: plan.timing_read(v) for k, v in kinds.items()}
     plan.timing(False)
+    shifted = pcg_shifted(plan, f, E, c.rtol, out, wall, torch)
     plan.close()
     its = np.array([s["iterations"] for s in stats])
     res = np.array([s["rel_residual"] for s in stats])
@@ -142,7 +143,31 @@ def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0):
             "max_true_rel_residual": float(res.max()),
             "kernel_time_s": kern_s, "achieved_GBs_all_kernels": alg_bytes / kern_s / 1e9,
             "dominant_kernel": dom, "dominant_GBs": dom_bytes / (kern[dom][0] / 1e3) / 1e9,
-            "kernels_ms": {k: v[0] for k, v in kern.items()}}
+            "kernels_ms": {k: v[0] for k, v in kern.items()}, "shifted": shifted}
+
+
+def pcg_shifted(plan, f, E, rtol, out, plain_s, torch, candidates=(0.02, 0.05, 0.1, 0.2), every=8, probe=32):
+    """The same solve with the shifted divisor K - E - i eta (an option beside
+    the paper's preconditioner): shifts tuned on every `every`-th energy by short
+    batched solves, each energy taking the shift of the nearest tuned one.
+    The reported time includes the tuning."""
+    sub = E[::every]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eta_sub = plan.sse_tune_shift(f, sub, candidates, probe_iters=probe, rtol=rtol)
+    eta = eta_sub[np.abs(E[:, None] - sub[None, :]).argmin(axis=1)]
+    t1 = time.perf_counter()
+    _, stats, code = plan.sse_solve(f, E, rtol=rtol, out=out, eta=eta)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    its = np.array([s["iterations"] for s in stats])
+    res = np.array([s["rel_residual"] for s in stats])
+    return {"time_to_tol_s": t2 - t0, "tune_s": t1 - t0, "solve_s": t2 - t1, "status": int(code),
+            "candidates": list(candidates), "tuned_on": int(len(sub)), "probe_iters": probe,
+            "eta": {f"{e:.3f}": float(v) for e, v in zip(sub, eta_sub)},
+            "iterations": {"min": int(its.min()), "mean": float(its.mean()), "max": int(its.max()),
+                           "total": int(its.sum())},
+            "max_true_rel_residual": float(res.max()), "speedup_vs_plain": plain_s / (t2 - t0)}
 
 
 def gpu_batch(sofft, wl, torch, steps, seed=2024, warmup=40):
@@ -217,6 +242,7 @@ def gpu_learned(sofft, wl, torch, epochs=30):
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     lp.close()
+    shifted = pcg_shifted(plan, f, np.asarray(E, dtype=np.float64), c.rtol, out, t_plain, torch)
     plan.close()
     i0 = np.array([q["iterations"] for q in st0])
     i1 = np.array([q["iterations"] for q in st1])
@@ -228,7 +254,8 @@ def gpu_learned(sofft, wl, torch, epochs=30):
             "learned": {"time_s": t_learned, "status": int(code1), "iterations_mean": float(i1.mean()),
                         "iterations_max": int(i1.max()), "fell_back": int(sum(q["fell_back"] for q in st1)),
                         "max_true_rel_residual": float(max(q["rel_residual"] for q in st1))},
-            "gain_time": t_plain / t_learned, "gain_iterations": float(i0.mean() / i1.mean())}
+            "gain_time": t_plain / t_learned, "gain_iterations": float(i0.mean() / i1.mean()),
+            "shifted_divisor": shifted}
 
 
 def cpu_baseline(wl, sample_steps, seed=1):
@@ -337,6 +364,10 @@ def main():
         log(f"  {pcg['energies']} energies in {pcg['time_to_tol_s']:.3f} s, iterations "
             f"{pcg['iterations']['min']}..{pcg['iterations']['max']} (mean {pcg['iterations']['mean']:.0f}), "
             f"{pcg['achieved_GBs_all_kernels']:.0f} GB/s over the fused passes")
+        sh = pcg["shifted"]
+        log(f"  shifted divisor (tuned on {sh['tuned_on']} energies): {sh['time_to_tol_s']:.3f} s "
+            f"(tuning {sh['tune_s']:.3f} s), iterations mean {sh['iterations']['mean']:.0f}, "
+            f"{sh['speedup_vs_plain']:.2f}x the plain solve")
 
     batch = None
     if not args.no_batch:
@@ -352,6 +383,9 @@ def main():
         log(f"  plain {learned['plain']['time_s']:.2f} s (mean {learned['plain']['iterations_mean']:.0f} it), "
             f"learned {learned['learned']['time_s']:.2f} s (mean {learned['learned']['iterations_mean']:.0f} it, "
             f"{learned['learned']['fell_back']} fell back); training {learned['train_s']:.1f} s")
+        sd = learned["shifted_divisor"]
+        log(f"  shifted divisor: {sd['time_to_tol_s']:.2f} s incl. tuning (mean {sd['iterations']['mean']:.0f} it), "
+            f"{sd['speedup_vs_plain']:.2f}x the plain solve")
 
     cpu = None
     if not args.no_cpu_baseline:
