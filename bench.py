@@ -295,8 +295,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures a single GPU: this build runs on one MI355X and has no multi-GPU path "
-              "(the workload would shard by runs/energies; see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures a single GPU: the library has no multi-GPU path (batched runs and energies "
+              "would shard across GPUs, one process each). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
