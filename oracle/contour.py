@@ -7,7 +7,13 @@ Sec. IV gives the contours compared in the paper:
 * SECS (Eq. qSECS): q = exp[i phi (|x| - r_s)/Dx_CS] for |x| > r_s with
   Dx_CS = r_max - r_s.  The paper fixes the end angle phi = pi/4; here the end
   angle is a parameter ``theta`` (pi/4 reproduces the paper);
-* off:    q = 1, z = x (plain SO-FFT).
+* off:    q = 1, z = x (plain SO-FFT);
+* TFECS (Eq. qTFECS): q = sqrt(1 + i y(s)) for |x| > r_s, s = (|x| - r_s)/Dx_CS,
+  y(s) = alpha [(1 - s)^-2 - (1 + s)^-2 - 4 s]; the parameter ``theta`` carries
+  alpha (the paper uses 0.5).  q is infinite at the box edge (s = 1), so only
+  1/q (= 0) is used there; z(x) has no closed form and is integrated
+  numerically (adaptive quadrature), finite at every node because the nodes
+  stop half a cell short of the edge.
 
 Readings:
 * r_max is the box edge b = L/2, so q reaches its end angle at the box edge.
@@ -15,10 +21,23 @@ Readings:
   |x| - r_s > 1e-9 h (h the grid step).  SECS is continuous there.
 """
 import numpy as np
+from scipy.integrate import quad
 
 SECS = "secs"
 SHARP = "sharp"
 OFF = "off"
+TFECS = "tfecs"
+
+
+def tfecs_y(s, alpha):
+    """y(s) = alpha [(1 - s)^-2 - (1 + s)^-2 - 4 s] of Eq. qTFECS."""
+    s = np.asarray(s, dtype=float)
+    return alpha * ((1.0 - s) ** -2 - (1.0 + s) ** -2 - 4.0 * s)
+
+
+def _tfecs_q_scalar(u, R0, D, alpha):
+    s = (u - R0) / D
+    return np.sqrt(1.0 + 1j * tfecs_y(s, alpha))
 
 
 def q_of_x(x, kind, R0, rmax, theta, h):
@@ -36,6 +55,13 @@ def q_of_x(x, kind, R0, rmax, theta, h):
     if kind == SHARP:
         out = (ax - R0) > 1e-9 * h
         q[out] = np.exp(1j * theta)
+        return q
+    if kind == TFECS:
+        D = rmax - R0
+        s = (ax - R0) / D
+        inner = (ax > R0) & (s < 1.0)
+        q[inner] = np.sqrt(1.0 + 1j * tfecs_y(s[inner], theta))
+        q[s >= 1.0] = complex(np.inf, 0.0)
         return q
     raise ValueError(kind)
 
@@ -57,5 +83,19 @@ def z_of_x(x, kind, R0, rmax, theta, h):
     if kind == SHARP:
         out = (ax - R0) > 1e-9 * h
         z[out] = np.sign(x[out]) * (R0 + (ax[out] - R0) * np.exp(1j * theta))
+        return z
+    if kind == TFECS:
+        D = rmax - R0
+        out = ax > R0
+        # int_{R0}^{|x|} q, accumulated over the sorted distinct |x| beyond R0
+        us = np.unique(ax[out])
+        acc, prev, val = 0.0 + 0.0j, R0, {}
+        for u in us:
+            re = quad(lambda t: _tfecs_q_scalar(t, R0, D, theta).real, prev, u, epsabs=1e-15, epsrel=2e-14, limit=200)[0]
+            im = quad(lambda t: _tfecs_q_scalar(t, R0, D, theta).imag, prev, u, epsabs=1e-15, epsrel=2e-14, limit=200)[0]
+            acc += re + 1j * im
+            val[u] = acc
+            prev = u
+        z[out] = np.sign(x[out]) * (R0 + np.array([val[u] for u in ax[out]]))
         return z
     raise ValueError(kind)

@@ -7,6 +7,8 @@ Readings:
   boundary (the paper's own picture of them as stitched together, Sec. III).
   The stencil between node N-1 and node 0 uses q at the box edge, q(b) = q(a).
 * q^{-1/2} takes the principal branch.
+* Where q is infinite (TFECS at the box edge), 1/q = 0: the stencil does not
+  couple through that cell edge.
 * C = K_s - K_FD is exactly zero on rows whose node and both neighbouring
   cell edges have q = 1 (Sec. II: C vanishes where q = 1), so C is a cyclic
   tridiagonal matrix that is non-zero only on the scaled strip.
@@ -21,6 +23,13 @@ def _neighbours(n):
     return (j + 1) % n, (j - 1) % n
 
 
+def _over(a, q):
+    """a / q, and 0 where q is infinite (the TFECS contour at the box edge)."""
+    inf = np.isinf(q.real) | np.isinf(q.imag)
+    safe = np.where(inf, 1.0, q)
+    return np.where(inf, 0.0, a / safe)
+
+
 def apply_Ks(psi, q, qm, h):
     """[K_s psi]_i of Sec. II Eq. Ks_FD, literally, with periodic indices.
 
@@ -28,8 +37,8 @@ def apply_Ks(psi, q, qm, h):
     n = len(q)
     jp, jm = _neighbours(n)
     qs = q ** -0.5
-    fwd = (qs[jp] * psi[jp] - qs * psi) / (qm * h)
-    bwd = (qs * psi - qs[jm] * psi[jm]) / (qm[jm] * h)
+    fwd = _over(qs[jp] * psi[jp] - qs * psi, qm) / h
+    bwd = _over(qs * psi - qs[jm] * psi[jm], qm[jm]) / h
     return -0.5 * qs / h * (fwd - bwd)
 
 
@@ -51,9 +60,9 @@ def remainder_matrix(q, qm, h):
     jp, jm = _neighbours(n)
     qs = q ** -0.5
     c = 1.0 / (2 * h * h)
-    up = -c * qs * qs[jp] / qm + c            # C_{j,j+1}
-    dn = -c * qs * qs[jm] / qm[jm] + c        # C_{j,j-1}
-    dg = c * (1.0 / q) * (1.0 / qm + 1.0 / qm[jm]) - 2 * c
+    up = -_over(c * qs * qs[jp], qm) + c            # C_{j,j+1}
+    dn = -_over(c * qs * qs[jm], qm[jm]) + c        # C_{j,j-1}
+    dg = c * (1.0 / q) * (_over(1.0, qm) + _over(1.0, qm[jm])) - 2 * c
     j = np.arange(n)
     rows = np.concatenate([j, j, j])
     cols = np.concatenate([j, jp, jm])

@@ -221,7 +221,7 @@ def test_strang_step_is_second_order_in_time():
     assert errs[1] / errs[2] == pytest.approx(4.0, rel=0.1)
 
 
-@pytest.mark.parametrize("kind", [contour.OFF, contour.SECS])
+@pytest.mark.parametrize("kind", [contour.OFF, contour.SECS, contour.TFECS])
 def test_free_gaussian_matches_closed_form_1d(kind):
     # Before the packet reaches R0, C acts on nothing: SO-FFT is exact for free motion.
     n, L = 512, 102.4
@@ -385,3 +385,51 @@ def test_shifted_cocg_reaches_the_dense_solution():
         assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
         its.append(it)
     assert len(set(its)) > 1   # the shift is in effect
+
+
+
+# ---- TFECS contour (Sec. IV, Eq. qTFECS)
+
+def test_tfecs_y_small_s_series():
+    """(1 - s)^-2 - (1 + s)^-2 = 4s + 8s^3 + 12s^5 + ..., so y(s) = alpha (8s^3 +
+    12s^5 + 16s^7 + 20s^9 + ...): the s^3 onset the paper states."""
+    s = np.array([0.01, 0.03, 0.05])
+    series = 0.5 * (8 * s ** 3 + 12 * s ** 5 + 16 * s ** 7 + 20 * s ** 9)
+    assert np.max(np.abs(contour.tfecs_y(s, 0.5) / series - 1)) < 1e-9
+
+
+def test_tfecs_z_grows_like_the_papers_log_form():
+    """z(x_N) ~ sqrt(alpha i) Dx ln(2 Dx/h) (Sec. IV): halving h at fixed Dx adds
+    sqrt(alpha i) Dx ln 2, up to O(h^2) terms."""
+    alpha, L, R0 = 0.5, 51.2, 20.0
+    D = L / 2 - R0
+    zN = [contour.z_of_x(np.array([L / 2 - h / 2]), contour.TFECS, R0, L / 2, alpha, h)[0]
+          for h in (0.2, 0.1, 0.05)]
+    want = np.sqrt(1j * alpha) * D * np.log(2.0)
+    e1 = abs((zN[1] - zN[0]) - want) / abs(want)
+    e2 = abs((zN[2] - zN[1]) - want) / abs(want)
+    assert e1 < 1e-3 and e2 < 3e-4
+    assert e1 / e2 == pytest.approx(4.0, rel=0.15)
+
+
+def test_tfecs_z_derivative_is_q():
+    """z(x) = int_0^x q (Eq. ECSintdef): central differences of z give q."""
+    alpha, L, R0, h = 0.5, 25.6, 8.0, 0.1
+    x = np.array([8.5, 10.0, 11.7, 12.5, -9.3])
+    d = 1e-4
+    zp = contour.z_of_x(x + d, contour.TFECS, R0, L / 2, alpha, h)
+    zm = contour.z_of_x(x - d, contour.TFECS, R0, L / 2, alpha, h)
+    q = contour.q_of_x(x, contour.TFECS, R0, L / 2, alpha, h)
+    assert np.max(np.abs((zp - zm) / (2 * d) - q) / np.abs(q)) < 1e-6
+
+
+def test_tfecs_box_edge_decouples_the_scaled_stencil():
+    """q is infinite at the box edge, so K_s does not couple through it and C's
+    coupling there is minus that of K_FD: C_{N,1} = C_{1,N} = 1/(2h^2)."""
+    n, L = 128, 25.6
+    ax = _axis(n, L, kind=contour.TFECS, R0=8.0, theta=0.5)
+    assert np.isinf(ax.qm[-1].real)
+    C = ax.C.toarray()
+    c = 1.0 / (2 * ax.h ** 2)
+    assert C[n - 1, 0] == c and C[0, n - 1] == c
+    assert np.all(np.isfinite(C))
