@@ -49,8 +49,13 @@ typedef enum { SOFFT_C128 = 0, SOFFT_C64 = 1 } sofft_dtype;
 
 /* ECS contour q(x), Sec. IV.  SOFFT_SECS: q = exp(i theta (|x|-R0)/(L/2-R0))
  * for |x| > R0 (Eq. qSECS with the end angle pi/4 replaced by theta).
- * SOFFT_SHARP: q = exp(i theta) for |x| - R0 > 1e-9 h.  SOFFT_ECS_OFF: q = 1. */
-typedef enum { SOFFT_SECS = 0, SOFFT_SHARP = 1, SOFFT_ECS_OFF = 2 } sofft_contour;
+ * SOFFT_SHARP: q = exp(i theta) for |x| - R0 > 1e-9 h.  SOFFT_ECS_OFF: q = 1.
+ * SOFFT_TFECS: q = sqrt(1 + i y(s)) for |x| > R0 (Eq. qTFECS), s = (|x|-R0)/(L/2-R0),
+ * y(s) = alpha [(1-s)^-2 - (1+s)^-2 - 4s], with alpha passed as theta (> 0;
+ * the paper uses 0.5).  q is infinite at the box edge, where the stencil of C
+ * then does not couple; z(x) = int q is integrated numerically (composite
+ * Gauss-Legendre) and is finite at every node. */
+typedef enum { SOFFT_SECS = 0, SOFFT_SHARP = 1, SOFFT_ECS_OFF = 2, SOFFT_TFECS = 3 } sofft_contour;
 
 /* The problem statement of Sec. II/III: grid, ECS radius and angle, and the
  * static part of U.  U(x, t) = V0(z(x)) + f(t) x with the soft-core Coulomb
@@ -63,7 +68,7 @@ typedef struct {
   int64_t n[2];      /* nodes per axis: n[0] = n_x (fast), n[1] = n_y (2D only) */
   double L[2];       /* box length per axis */
   double R0[2];      /* ECS radius per axis, 0 < R0 < L/2 (ignored if contour off) */
-  double theta;      /* ECS angle, 0 < theta < pi/2 */
+  double theta;      /* ECS angle, 0 < theta < pi/2 (SECS, sharp); alpha > 0 (TFECS) */
   int32_t contour;   /* sofft_contour */
   double charge;     /* soft-core strength (>= 0) */
   double a2;         /* soft-core parameter a^2 (> 0 if charge > 0) */

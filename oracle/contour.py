@@ -91,8 +91,8 @@ def z_of_x(x, kind, R0, rmax, theta, h):
         us = np.unique(ax[out])
         acc, prev, val = 0.0 + 0.0j, R0, {}
         for u in us:
-            re = quad(lambda t: _tfecs_q_scalar(t, R0, D, theta).real, prev, u, epsabs=1e-15, epsrel=2e-14, limit=200)[0]
-            im = quad(lambda t: _tfecs_q_scalar(t, R0, D, theta).imag, prev, u, epsabs=1e-15, epsrel=2e-14, limit=200)[0]
+            re = quad(lambda t: _tfecs_q_scalar(t, R0, D, theta).real, prev, u, epsabs=1e-13, epsrel=1e-13, limit=200)[0]
+            im = quad(lambda t: _tfecs_q_scalar(t, R0, D, theta).imag, prev, u, epsabs=1e-13, epsrel=1e-13, limit=200)[0]
             acc += re + 1j * im
             val[u] = acc
             prev = u

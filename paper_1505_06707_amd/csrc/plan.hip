@@ -3,6 +3,7 @@
 // device copies.
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "internal.hpp"
 #include "line_fft.hpp"
@@ -42,8 +43,19 @@ bool supported_length(int64_t n) {
   }
 }
 
+// TFECS (Sec. IV, Eq. qTFECS): q = sqrt(1 + i y(s)), s = (|x| - R0)/(L/2 - R0),
+// y(s) = alpha [(1 - s)^-2 - (1 + s)^-2 - 4 s], alpha carried by theta.  q is
+// infinite at the box edge (s = 1); that point is represented by an infinite
+// real part and only ever divides (1/q = 0 there).
+static zc tfecs_q(double ax, const Axis& a) {
+  const double s = (ax - a.R0) / (a.L / 2 - a.R0);
+  if (s >= 1.0) return zc(INFINITY, 0.0);
+  const double y = a.theta * (1.0 / ((1.0 - s) * (1.0 - s)) - 1.0 / ((1.0 + s) * (1.0 + s)) - 4.0 * s);
+  return std::sqrt(zc(1.0, y));
+}
+
 // q(x) of the contour (Sec. IV): sharp rotation, smooth SECS (Eq. qSECS with
-// end angle theta at the box edge), or no scaling.
+// end angle theta at the box edge), TFECS, or no scaling.
 static zc contour_q(double x, const Axis& a) {
   const double ax = std::fabs(x);
   switch (a.contour) {
@@ -53,9 +65,54 @@ static zc contour_q(double x, const Axis& a) {
     case SOFFT_SHARP:
       if (ax - a.R0 > 1e-9 * a.h) return std::polar(1.0, a.theta);
       return 1.0;
+    case SOFFT_TFECS:
+      if (ax > a.R0) return tfecs_q(ax, a);
+      return 1.0;
     default:
       return 1.0;
   }
+}
+
+// n-point Gauss-Legendre nodes and weights on [-1, 1]: roots of P_n by Newton's
+// method from the usual cosine guesses, P_n and P_n' by the three-term
+// recurrence.
+static void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w) {
+  const double pi = 3.14159265358979323846;
+  t.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    t[i] = x;
+    w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+}
+
+// int_u0^u1 q for TFECS by composite 20-point Gauss-Legendre, 4 panels per
+// call (the integrand is analytic on the interval: its singularity at the box
+// edge lies at least half a cell beyond any node).
+static zc tfecs_integral(double u0, double u1, const Axis& a) {
+  static std::vector<double> t, w;
+  if (t.empty()) gauss_legendre(20, t, w);
+  zc acc = 0.0;
+  const int panels = 4;
+  const double hp = (u1 - u0) / panels;
+  for (int k = 0; k < panels; ++k) {
+    const double c = u0 + hp * (k + 0.5), r = hp / 2;
+    for (size_t i = 0; i < t.size(); ++i) acc += w[i] * r * tfecs_q(c + r * t[i], a);
+  }
+  return acc;
 }
 
 // z(x) = int_0^x q (Sec. II, Eq. ECSintdef) in closed form for each contour.
@@ -73,10 +130,16 @@ static zc contour_z(double x, const Axis& a) {
     case SOFFT_SHARP:
       if (ax - a.R0 > 1e-9 * a.h) return sg * (a.R0 + (ax - a.R0) * std::polar(1.0, a.theta));
       return x;
+    case SOFFT_TFECS:
+      // no closed form: callers integrate (tfecs_integral); see build_axis
+      return x;
     default:
       return x;
   }
 }
+
+// a / q, and 0 where q is infinite (TFECS at the box edge).
+static zc over_q(zc num, zc q) { return std::isinf(q.real()) ? zc(0.0) : num / q; }
 
 sofft_status build_axis(Axis& a, int64_t n, double L, double R0, double theta, int contour) {
   a.n = n;
@@ -103,6 +166,22 @@ sofft_status build_axis(Axis& a, int64_t n, double L, double R0, double theta, i
     a.qm[j] = contour_q(a.xm[j], a);
     a.z[j] = contour_z(a.x[j], a);
   }
+  if (contour == SOFFT_TFECS) {
+    // z = sign(x) (R0 + int_R0^|x| q), accumulated node by node outward from
+    // R0 on each side (the nodes are symmetric about 0).
+    for (int side = 0; side < 2; ++side) {
+      zc acc = 0.0;
+      double prev = R0;
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t j = side ? i : n - 1 - i;   // outward: increasing |x|
+        const double ax = std::fabs(a.x[j]);
+        if ((side == 1 && a.x[j] < 0) || (side == 0 && a.x[j] > 0) || ax <= R0) continue;
+        acc += tfecs_integral(prev, ax, a);
+        prev = ax;
+        a.z[j] = (a.x[j] < 0 ? -1.0 : 1.0) * (R0 + acc);
+      }
+    }
+  }
   // C = K_s - K_FD from the three-point stencils of Eqs. Ks_FD and K_FD,
   // periodic in j: the midpoint left of node 0 is the box edge (index n-1).
   a.cdn.assign(n, 0.0);
@@ -114,9 +193,9 @@ sofft_status build_axis(Axis& a, int64_t n, double L, double R0, double theta, i
   for (int64_t j = 0; j < n; ++j) {
     const int64_t jp = (j + 1) % n, jm = (j + n - 1) % n;
     const zc qr = a.qm[j], ql = a.qm[jm];
-    a.cup[j] = -c * qs[j] * qs[jp] / qr + c;
-    a.cdn[j] = -c * qs[j] * qs[jm] / ql + c;
-    a.cdg[j] = c * (1.0 / a.q[j]) * (1.0 / qr + 1.0 / ql) - 2.0 * c;
+    a.cup[j] = -over_q(c * qs[j] * qs[jp], qr) + c;
+    a.cdn[j] = -over_q(c * qs[j] * qs[jm], ql) + c;
+    a.cdg[j] = c * (1.0 / a.q[j]) * (over_q(1.0, qr) + over_q(1.0, ql)) - 2.0 * c;
   }
   // The strip: nodes whose row of C is non-zero.  It must be one cyclic run
   // that leaves part of the axis unscaled.
@@ -313,12 +392,17 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
     set_error("dtype must be SOFFT_C128 or SOFFT_C64");
     return SOFFT_EINVAL;
   }
-  if (p.contour != SOFFT_SECS && p.contour != SOFFT_SHARP && p.contour != SOFFT_ECS_OFF) {
+  if (p.contour != SOFFT_SECS && p.contour != SOFFT_SHARP && p.contour != SOFFT_ECS_OFF &&
+      p.contour != SOFFT_TFECS) {
     set_error("unknown contour");
     return SOFFT_EINVAL;
   }
-  if (p.contour != SOFFT_ECS_OFF && !(p.theta > 0 && p.theta < 1.5707963267948966)) {
+  if ((p.contour == SOFFT_SECS || p.contour == SOFFT_SHARP) && !(p.theta > 0 && p.theta < 1.5707963267948966)) {
     set_error("theta must lie in (0, pi/2)");
+    return SOFFT_EINVAL;
+  }
+  if (p.contour == SOFFT_TFECS && !(p.theta > 0 && std::isfinite(p.theta))) {
+    set_error("the TFECS parameter alpha (theta) must be positive and finite");
     return SOFFT_EINVAL;
   }
   if (!(p.charge >= 0) || (p.charge > 0 && !(p.a2 > 0))) {

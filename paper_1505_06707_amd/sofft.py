@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsofft.so")
 
 C128, C64 = 0, 1
-SECS, SHARP, ECS_OFF = 0, 1, 2
+SECS, SHARP, ECS_OFF, TFECS = 0, 1, 2, 3
 
 _STATUS = {0: "SOFFT_OK", -1: "SOFFT_EINVAL", -2: "SOFFT_EUNSUPPORTED", -3: "SOFFT_EHIP",
            -4: "SOFFT_ENOMEM", 1: "SOFFT_NOT_CONVERGED", 2: "SOFFT_BREAKDOWN"}

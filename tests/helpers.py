@@ -5,7 +5,7 @@ import numpy as np
 from oracle import contour as oc
 from oracle import tdse as ot
 
-CONTOURS = {"secs": (oc.SECS, 0), "sharp": (oc.SHARP, 1), "off": (oc.OFF, 2)}
+CONTOURS = {"secs": (oc.SECS, 0), "sharp": (oc.SHARP, 1), "off": (oc.OFF, 2), "tfecs": (oc.TFECS, 3)}
 
 
 def oracle_axis(n, L, R0, theta, kind):

@@ -78,7 +78,7 @@ def test_1d_parity_all_lengths(n):
     assert rel_l2(g, o) < TOL64
 
 
-@pytest.mark.parametrize("kind", ["secs", "sharp", "off"])
+@pytest.mark.parametrize("kind", ["secs", "sharp", "off", "tfecs"])
 def test_1d_parity_contours(kind):
     print(f"1D contour={kind}", flush=True)
     n, L, R0 = 512, 102.4, 30.0
@@ -115,6 +115,23 @@ def test_2d_parity_shapes(nx, ny):
     f = wl.Pulse(E0=0.08, omega=0.3, cycles=2).at_midpoints(0.0, 0.05, 40)
     args = (nx, ny, Lx, Ly, R0x, R0y, 0.5, "secs", 1.0, 0.64, psi0, 0.05, f)
     assert rel_l2(run_gpu_2d(*args), oracle_2d(*args)) < TOL64
+
+
+def test_2d_tfecs_parity():
+    """TFECS on both axes (Eq. qTFECS, alpha = 0.5): a packet driven into the
+    scaled strips, with the soft-core potential and the pulse."""
+    print("2D TFECS 128x96", flush=True)
+    nx, ny, h = 128, 96, 0.2
+    Lx, Ly = nx * h, ny * h
+    R0x, R0y = 0.7 * Lx / 2, 0.7 * Ly / 2
+    ax, ay = ot.Axis(nx, Lx, R0=R0x), ot.Axis(ny, Ly, R0=R0y)
+    psi0 = wl.gaussian_2d(ax.x, ay.x, x0=0.5, y0=-0.3, px=2.0, py=-1.5)
+    f = wl.Pulse(E0=0.05, omega=0.3, cycles=2).at_midpoints(0.0, 0.05, 120)
+    args = (nx, ny, Lx, Ly, R0x, R0y, 0.5, "tfecs", 1.0, 0.64, psi0, 0.05, f)
+    g = run_gpu_2d(*args)
+    o = oracle_2d(*args)
+    assert rel_l2(g, o) < TOL64
+    assert np.linalg.norm(g) < np.linalg.norm(psi0)   # the strips absorb
 
 
 def test_2d_full_size_parity_few_steps():
