@@ -146,6 +146,31 @@ def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0):
             "kernels_ms": {k: v[0] for k, v in kern.items()}, "shifted": shifted}
 
 
+def gpu_pcg_tfecs(sofft, wl, torch, n_energies=32, seed=0):
+    """The 512^2 stationary workload on the TFECS contour (Eq. qTFECS, alpha =
+    0.5), where the paper finds the plain FFT preconditioner slow: 32 energies
+    in [0.05, 2.0] with the paper's divisor, then with tuned shifts."""
+    c = wl.SSE_2D
+    plan = sofft.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=0.5, contour=sofft.TFECS,
+                      charge=c.charge, a2=c.a2)
+    f = torch.from_numpy(-wl.smooth_source(c.n, c.n, seed=seed)).cuda()
+    E = np.linspace(c.E_lo, c.E_hi, n_energies)
+    out = torch.empty((len(E), c.n, c.n), dtype=torch.complex128, device="cuda")
+    plan.sse_solve(f, E[:2], rtol=c.rtol, out=out[:2], maxit=50000)    # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, stats, code = plan.sse_solve(f, E, rtol=c.rtol, out=out, maxit=50000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    shifted = pcg_shifted(plan, f, E, c.rtol, out, wall, torch, every=4)
+    plan.close()
+    its = np.array([q["iterations"] for q in stats])
+    return {"workload": f"{c.n}^2 TFECS alpha 0.5, {len(E)} energies in [{c.E_lo}, {c.E_hi}], rtol {c.rtol}",
+            "time_to_tol_s": wall, "status": int(code),
+            "iterations": {"min": int(its.min()), "mean": float(its.mean()), "max": int(its.max())},
+            "max_true_rel_residual": float(max(q["rel_residual"] for q in stats)), "shifted": shifted}
+
+
 def pcg_shifted(plan, f, E, rtol, out, plain_s, torch, candidates=(0.02, 0.05, 0.1, 0.2), every=8, probe=32):
     """The same solve with the shifted divisor K - E - i eta (an option beside
     the paper's preconditioner): shifts tuned on every `every`-th energy by short
@@ -368,6 +393,12 @@ def main():
         log(f"  shifted divisor (tuned on {sh['tuned_on']} energies): {sh['time_to_tol_s']:.3f} s "
             f"(tuning {sh['tune_s']:.3f} s), iterations mean {sh['iterations']['mean']:.0f}, "
             f"{sh['speedup_vs_plain']:.2f}x the plain solve")
+        log("SSE 512^2 on the TFECS contour, 32 energies")
+        pcg["tfecs"] = gpu_pcg_tfecs(sofft, wl, torch)
+        tf = pcg["tfecs"]
+        log(f"  plain {tf['time_to_tol_s']:.3f} s (mean {tf['iterations']['mean']:.0f} it); shifted "
+            f"{tf['shifted']['time_to_tol_s']:.3f} s incl. tuning (mean {tf['shifted']['iterations']['mean']:.0f} it), "
+            f"{tf['shifted']['speedup_vs_plain']:.2f}x")
 
     batch = None
     if not args.no_batch:
