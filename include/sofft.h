@@ -171,6 +171,23 @@ sofft_status sofft_sse_solve_shifted(sofft_plan* plan, const void* f, int32_t f_
 sofft_status sofft_sse_apply_shifted(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double eta,
                                      double field, void* stream);
 
+/* The banded ECS eigen-preconditioner of Sec. III (Eqs. Prec_eigen_eq, K_l,
+ * PreconFFT_ECS) for one axis of a problem, computed on the host (no device
+ * work; the stationary solver builds the same tables itself).  The spectrum,
+ * in FFT index order, is cut into bands: {k_0} and {k_N/2} alone, the positive
+ * momenta from k_1 outward in bands of 10 with the remainder joined to the band
+ * next to k_N/2 (at most 19), the negative momenta mirrored.  On each band
+ * [K_l]_{nm} = 1/2 k_n k_m Q(m - n), Q(d) = (1/N) sum_j q_j^-2 exp(2 pi i d x_j / L),
+ * is diagonalised by a complex orthogonal X (X^T X = 1).
+ *   lambda_out   host, 2 n doubles: eigenvalue of the row n of X (re, im)
+ *   x_rows_out   host, 2 n 19 doubles: row n of X restricted to its band,
+ *                x_rows[n][i] = X[n][band_start[n] + i], i < band_width[n], zero-padded
+ *   band_start, band_width  host, n int32 each
+ * n = prob->n[axis], even and >= 4.  SOFFT_EINVAL for a bad problem;
+ * SOFFT_EUNSUPPORTED if a band's eigen-decomposition fails. */
+sofft_status sofft_band_tables(const sofft_problem* prob, int32_t axis, double* lambda_out, double* x_rows_out,
+                               int32_t* band_start, int32_t* band_width);
+
 /* Choose a divisor shift per energy for sofft_sse_solve_shifted by short
  * solves of the problem itself: all nE * ncand (energy, candidate) systems
  * run as one batched COCG limited to probe_iters iterations.  A candidate

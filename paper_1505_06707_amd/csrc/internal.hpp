@@ -51,7 +51,23 @@ struct Axis {
   int levels = 0;
   DevBuf kin_full64, kin_half64;
   DevBuf alpha64, gamma64, binv64;
+  // Banded ECS eigen-preconditioner of this axis (built on first use).
+  bool have_bands = false;
+  DevBuf band_lam, band_xr, band_xc, band_start, band_width;
 };
+
+// Banded ECS eigen-preconditioner (banded.hip), Sec. III: bands of at most
+// kBandMax consecutive momenta per axis.  Per FFT index n (n is the band row nu
+// for X and the column m for X^T):
+//   lam[n]                 eigenvalue of K_l belonging to row n
+//   xr[i * n_axis + n]     X[n][s_n + i]   (i < w_n): y_n = sum_i xr v[s_n + i]
+//   xc[i * n_axis + n]     X[s_n + i][n]   (i < w_n): z_n = sum_i xc y[s_n + i]
+//   start[n] = s_n, width[n] = w_n of the band holding n
+constexpr int kBandWidth = 10;
+constexpr int kBandMax = 2 * kBandWidth - 1;
+sofft_status band_tables(const Axis& a, std::vector<zc>& lam, std::vector<zc>& xr, std::vector<zc>& xc,
+                         std::vector<int32_t>& start, std::vector<int32_t>& width);
+sofft_status ensure_bands(Axis& a);
 
 // Optional per-launch event timing (measurement aid).
 struct Timing {

@@ -357,8 +357,9 @@ sofft_status ensure_dt(Axis& a, double dt) {
 
 void free_axis(Axis& a) {
   for (DevBuf* b : {&a.tw64, &a.x_dev, &a.z_dev, &a.cstrip64, &a.kin_full64, &a.kin_half64, &a.alpha64,
-                    &a.gamma64, &a.binv64})
+                    &a.gamma64, &a.binv64, &a.band_lam, &a.band_xr, &a.band_xc, &a.band_start, &a.band_width})
     dev_free(*b);
+  a.have_bands = false;
 }
 
 }  // namespace sofft

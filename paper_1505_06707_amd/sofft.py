@@ -74,6 +74,8 @@ _SIGS = {
                                                ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_sse_apply_shifted": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]),
+    "sofft_band_tables": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_sse_tune_shift": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -321,6 +323,23 @@ class Plan:
         out = ctypes.c_double()
         _check(lib().sofft_norm2(self._h, ptr, ctypes.byref(out), _stream(stream)))
         return out.value
+
+
+BAND_MAX = 19
+
+
+def band_tables(prob, axis=0):
+    """Host tables of the banded ECS eigen-preconditioner for one axis of a
+    problem (sofft_band_tables): (lambda [n], X rows [n][19], start [n], width [n])."""
+    n = int(prob.n[axis])
+    lam = np.zeros(2 * n, dtype=np.float64)
+    xr = np.zeros(2 * n * BAND_MAX, dtype=np.float64)
+    st = np.zeros(n, dtype=np.int32)
+    wd = np.zeros(n, dtype=np.int32)
+    _check(lib().sofft_band_tables(ctypes.byref(prob), int(axis), lam.ctypes.data_as(ctypes.c_void_p),
+                                   xr.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p),
+                                   wd.ctypes.data_as(ctypes.c_void_p)))
+    return lam.view(np.complex128), xr.view(np.complex128).reshape(n, BAND_MAX), st, wd
 
 
 def problem(n, L, R0=None, theta=0.5, contour=SECS, charge=1.0, a2=2.0, dtype=C128):
