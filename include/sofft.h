@@ -171,6 +171,21 @@ sofft_status sofft_sse_solve_shifted(sofft_plan* plan, const void* f, int32_t f_
 sofft_status sofft_sse_apply_shifted(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double eta,
                                      double field, void* stream);
 
+/* sofft_sse_solve with the banded ECS eigen-preconditioner of Sec. III,
+ * Eq. PreconFFT_ECS, instead of Eq. PreconFFT: in 2D
+ *   P^-1 = F^-1 (X_x (x) X_y)^T (lambda_x + lambda_y - E)^-1 (X_x (x) X_y) F,
+ * with X and lambda of each axis as sofft_band_tables describes (built on the
+ * first call and kept by the plan).  Arguments, workspace, blocking and status
+ * as sofft_sse_solve; SOFFT_EUNSUPPORTED if a band's eigen-decomposition fails. */
+sofft_status sofft_sse_solve_banded(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
+                                    int32_t nE, double field, void* x_out, double rtol, int32_t maxit,
+                                    sofft_solve_stats* stats, void* stream);
+
+/* sofft_sse_apply with the banded preconditioner (op 1: w = P^-1 v of
+ * Eq. PreconFFT_ECS; op 0 as sofft_sse_apply).  Asynchronous. */
+sofft_status sofft_sse_apply_banded(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double field,
+                                    void* stream);
+
 /* The banded ECS eigen-preconditioner of Sec. III (Eqs. Prec_eigen_eq, K_l,
  * PreconFFT_ECS) for one axis of a problem, computed on the host (no device
  * work; the stationary solver builds the same tables itself).  The spectrum,

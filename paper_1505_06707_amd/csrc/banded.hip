@@ -140,6 +140,19 @@ sofft_status ensure_bands(Axis& a) {
   std::vector<int32_t> st, wd;
   sofft_status s = band_tables(a, lam, xr, xc, st, wd);
   if (s != SOFFT_OK) return s;
+  // The kernels transform with the plain DFT, exp(-2 pi i m j / n); the basis
+  // of Sec. II has F_mj = exp(-i k_m x_j)/sqrt(n) = ph_m exp(-2 pi i m j / n)/sqrt(n)
+  // with ph_m = exp(-i k_m x_0) on the cell-centred grid.  A diagonal divisor does
+  // not see ph; X does: in the DFT basis it is X ph (columns scaled by ph_m)
+  // and X^T becomes ph^-1 X^T (rows scaled by 1/ph_n).
+  const int64_t n = a.n;
+  std::vector<zc> ph(n);
+  for (int64_t m = 0; m < n; ++m) ph[m] = std::exp(zc(0.0, -a.k[m] * a.x[0]));
+  for (int64_t idx = 0; idx < n; ++idx)
+    for (int i = 0; i < wd[idx]; ++i) {
+      xr[size_t(i) * n + idx] *= ph[st[idx] + i];
+      xc[size_t(i) * n + idx] /= ph[idx];
+    }
   if ((s = dev_upload(a.band_lam, lam.data(), lam.size() * sizeof(zc))) != SOFFT_OK) return s;
   if ((s = dev_upload(a.band_xr, xr.data(), xr.size() * sizeof(zc))) != SOFFT_OK) return s;
   if ((s = dev_upload(a.band_xc, xc.data(), xc.size() * sizeof(zc))) != SOFFT_OK) return s;

@@ -161,9 +161,9 @@ sofft_status lp_apply(LpNet& net, const cx<double>* r, cx<double>* z, int B, int
 // preconditioner per energy.
 sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E_host, int nE, double field,
                        void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s,
-                       LpNet* lp = nullptr, int patience = 0, const double* eta_host = nullptr);
+                       LpNet* lp = nullptr, int patience = 0, const double* eta_host = nullptr, int banded = 0);
 sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s,
-                       double eta = 0.0);
+                       double eta = 0.0, int banded = 0);
 sofft_status sse_tune_shift(Plan& p, const void* f, const double* E_host, int nE, double field,
                             const double* cand, int ncand, int probe_iters, double rtol, void* scratch_x,
                             double* eta_out, hipStream_t s);

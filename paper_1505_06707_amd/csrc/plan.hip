@@ -50,7 +50,10 @@ bool supported_length(int64_t n) {
 static zc tfecs_q(double ax, const Axis& a) {
   const double s = (ax - a.R0) / (a.L / 2 - a.R0);
   if (s >= 1.0) return zc(INFINITY, 0.0);
-  const double y = a.theta * (1.0 / ((1.0 - s) * (1.0 - s)) - 1.0 / ((1.0 + s) * (1.0 + s)) - 4.0 * s);
+  // alpha [(1 - s)^-2 - (1 + s)^-2 - 4 s] = 4 alpha s^3 (2 - s^2)/(1 - s^2)^2, the
+  // second form free of cancellation at small s
+  const double u = 1.0 - s * s;
+  const double y = 4.0 * a.theta * s * s * s * (2.0 - s * s) / (u * u);
   return std::sqrt(zc(1.0, y));
 }
 
@@ -551,6 +554,31 @@ sofft_status sofft_sse_apply_shifted(sofft_plan* plan, int32_t op, const void* v
     return SOFFT_EINVAL;
   }
   return sse_apply(*plan, op, v, w, E, field, reinterpret_cast<hipStream_t>(stream), eta);
+}
+
+sofft_status sofft_sse_solve_banded(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
+                                    int32_t nE, double field, void* x_out, double rtol, int32_t maxit,
+                                    sofft_solve_stats* stats, void* stream) {
+  if (!plan || !f || !E_host || nE <= 0 || !x_out || !(rtol > 0) || maxit <= 0 || !std::isfinite(field)) {
+    set_error("bad argument to sofft_sse_solve_banded");
+    return SOFFT_EINVAL;
+  }
+  for (int e = 0; e < nE; ++e)
+    if (!std::isfinite(E_host[e])) {
+      set_error("energies must be finite");
+      return SOFFT_EINVAL;
+    }
+  return sse_solve(*plan, f, f_per_energy, E_host, nE, field, x_out, rtol, maxit, stats,
+                   reinterpret_cast<hipStream_t>(stream), nullptr, 0, nullptr, 1);
+}
+
+sofft_status sofft_sse_apply_banded(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double field,
+                                    void* stream) {
+  if (!plan || !v || !w || (op != 0 && op != 1) || !std::isfinite(E) || !std::isfinite(field)) {
+    set_error("bad argument to sofft_sse_apply_banded");
+    return SOFFT_EINVAL;
+  }
+  return sse_apply(*plan, op, v, w, E, field, reinterpret_cast<hipStream_t>(stream), 0.0, 1);
 }
 
 sofft_status sofft_sse_tune_shift(sofft_plan* plan, const void* f, const double* E_host, int32_t nE, double field,

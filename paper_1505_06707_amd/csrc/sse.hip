@@ -62,6 +62,19 @@ struct SseArgs {
   const cx<double>* V;         // U on the grid, [n_y][n_x]
   const double* E;             // [nE]
   const double* eta;           // [nE] shift of the preconditioner's divisor (K - E - i eta), or null
+  // banded ECS eigen-preconditioner (Eq. PreconFFT_ECS) instead of Eq. PreconFFT when banded = 1;
+  // per axis the tables of ensure_bands (x: rows of the grid, y: columns)
+  int banded;
+  const cx<double>* bx_lam;
+  const cx<double>* bx_xr;
+  const cx<double>* bx_xc;
+  const int* bx_start;
+  const int* bx_width;
+  const cx<double>* by_lam;
+  const cx<double>* by_xr;
+  const cx<double>* by_xc;
+  const int* by_start;
+  const int* by_width;
   CocgScalars* sc;             // [nE]
   double* part_rr;             // [nE][nblk_row]
   cx<double>* part_rz;         // [nE][nblk_row]
@@ -242,8 +255,31 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_col_mv(SseArgs a, int want,
   }
 }
 
-// ---------------------------------------------------------------- K4: update and forward row FFT
+// Block-diagonal multiply along a line in Fourier space (Eq. PreconFFT_ECS):
+// v[n] <- sum_{i < width[n]} coef[i * N + n] v[start[n] + i], the line held
+// as v[s] = element t + TPL s (natural FFT index order) and passed through the
+// LDS view L.  Every thread of the block calls it (block barriers).
 template <int N>
+__device__ __forceinline__ void band_apply(cx<double> (&v)[Shape<N>::P], const LineLDS<double>& L, int t,
+                                           const cx<double>* __restrict__ coef, const int* __restrict__ start,
+                                           const int* __restrict__ width) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < P; ++s) L[t + TPL * s] = v[s];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int n = t + TPL * s, st = start[n], w = width[n];
+    cx<double> acc{0.0, 0.0};
+    for (int i = 0; i < w; ++i) acc = cfma(acc, coef[size_t(i) * N + n], L[st + i]);
+    v[s] = acc;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- K4: update and forward row FFT
+template <int N, bool BANDED>
 __global__ void __launch_bounds__(kSseThreads) k_sse_row_upd(SseArgs a, int want, int mode) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
@@ -284,6 +320,7 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_row_upd(SseArgs a, int want
     v[s] = rv;
   }
   fft<double, N, -1>(v, L, t, a.twx);
+  if constexpr (BANDED) band_apply<N>(v, L, t, a.bx_xr, a.bx_start, a.bx_width);   // X_x
   if (live) {
 #pragma unroll
     for (int s = 0; s < P; ++s) a.s[off + t + TPL * s] = v[s];
@@ -293,7 +330,7 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_row_upd(SseArgs a, int want
 }
 
 // ---------------------------------------------------------------- K5: column part of P^-1
-template <int N>
+template <int N, bool BANDED>
 __global__ void __launch_bounds__(kSseThreads) k_sse_col_prec(SseArgs a, int want) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
@@ -314,7 +351,18 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_col_prec(SseArgs a, int wan
   const double kx = kval(ccol, a.nx, a.Lx), E = a.E[e];
   const double eta = a.eta ? a.eta[e] : 0.0;
   const double scale = 1.0 / (double(a.nx) * double(N));
-  if (eta == 0.0) {   // uniform over the block
+  if constexpr (BANDED) {
+    // X_y, then 1/(lambda_x + lambda_y - E), then X_y^T (Eq. PreconFFT_ECS in 2D)
+    band_apply<N>(v, L, t, a.by_xr, a.by_start, a.by_width);
+    const cx<double> lx = a.bx_lam[ccol];
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const cx<double> d = lx + a.by_lam[t + TPL * s] - cx<double>{E, 0.0};
+      const double q = scale / (d.re * d.re + d.im * d.im);
+      v[s] = cmul(v[s], cx<double>{q * d.re, -q * d.im});
+    }
+    band_apply<N>(v, L, t, a.by_xc, a.by_start, a.by_width);
+  } else if (eta == 0.0) {   // uniform over the block (the plain kernels compile without the banded branch)
 #pragma unroll
     for (int s = 0; s < P; ++s) {
       const double ky = kval(t + TPL * s, N, a.Ly);
@@ -340,7 +388,7 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_col_prec(SseArgs a, int wan
 }
 
 // ---------------------------------------------------------------- K6: inverse row FFT and r^T z
-template <int N>
+template <int N, bool BANDED>
 __global__ void __launch_bounds__(kSseThreads) k_sse_row_prec(SseArgs a, int want) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
@@ -360,6 +408,7 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_row_prec(SseArgs a, int wan
     v[s] = live ? a.s[off + t + TPL * s] : cx<double>{0.0, 0.0};
     rv[s] = live ? a.r[off + t + TPL * s] : cx<double>{0.0, 0.0};
   }
+  if constexpr (BANDED) band_apply<N>(v, L, t, a.bx_xc, a.bx_start, a.bx_width);   // X_x^T
   fft<double, N, +1>(v, L, t, a.twx);
   cx<double> dot{0.0, 0.0}, dot_old{0.0, 0.0};
 #pragma unroll
@@ -611,19 +660,37 @@ static sofft_status sse_launch(SseKernel k, const SseArgs& a, int want, int mode
       k_sse_col_mv<NY><<<gcol, lpby * TPLY, ldsy, s>>>(a, want, mode);
       break;
     case kK4:
-      if ((st = sse_set_lds(k_sse_row_upd<NX>, ldsx)) != SOFFT_OK) return st;
-      if ((st = tm.begin(SOFFT_KERNEL_SSE_ROW_UPD, s)) != SOFFT_OK) return st;
-      k_sse_row_upd<NX><<<grow, lpbx * TPLX, ldsx, s>>>(a, want, mode);
+      if (a.banded) {
+        if ((st = sse_set_lds(k_sse_row_upd<NX, true>, ldsx)) != SOFFT_OK) return st;
+        if ((st = tm.begin(SOFFT_KERNEL_SSE_ROW_UPD, s)) != SOFFT_OK) return st;
+        k_sse_row_upd<NX, true><<<grow, lpbx * TPLX, ldsx, s>>>(a, want, mode);
+      } else {
+        if ((st = sse_set_lds(k_sse_row_upd<NX, false>, ldsx)) != SOFFT_OK) return st;
+        if ((st = tm.begin(SOFFT_KERNEL_SSE_ROW_UPD, s)) != SOFFT_OK) return st;
+        k_sse_row_upd<NX, false><<<grow, lpbx * TPLX, ldsx, s>>>(a, want, mode);
+      }
       break;
     case kK5:
-      if ((st = sse_set_lds(k_sse_col_prec<NY>, ldsy)) != SOFFT_OK) return st;
-      if ((st = tm.begin(SOFFT_KERNEL_SSE_COL_PREC, s)) != SOFFT_OK) return st;
-      k_sse_col_prec<NY><<<gcol, lpby * TPLY, ldsy, s>>>(a, want);
+      if (a.banded) {
+        if ((st = sse_set_lds(k_sse_col_prec<NY, true>, ldsy)) != SOFFT_OK) return st;
+        if ((st = tm.begin(SOFFT_KERNEL_SSE_COL_PREC, s)) != SOFFT_OK) return st;
+        k_sse_col_prec<NY, true><<<gcol, lpby * TPLY, ldsy, s>>>(a, want);
+      } else {
+        if ((st = sse_set_lds(k_sse_col_prec<NY, false>, ldsy)) != SOFFT_OK) return st;
+        if ((st = tm.begin(SOFFT_KERNEL_SSE_COL_PREC, s)) != SOFFT_OK) return st;
+        k_sse_col_prec<NY, false><<<gcol, lpby * TPLY, ldsy, s>>>(a, want);
+      }
       break;
     case kK6:
-      if ((st = sse_set_lds(k_sse_row_prec<NX>, ldsx)) != SOFFT_OK) return st;
-      if ((st = tm.begin(SOFFT_KERNEL_SSE_ROW_PREC, s)) != SOFFT_OK) return st;
-      k_sse_row_prec<NX><<<grow, lpbx * TPLX, ldsx, s>>>(a, want);
+      if (a.banded) {
+        if ((st = sse_set_lds(k_sse_row_prec<NX, true>, ldsx)) != SOFFT_OK) return st;
+        if ((st = tm.begin(SOFFT_KERNEL_SSE_ROW_PREC, s)) != SOFFT_OK) return st;
+        k_sse_row_prec<NX, true><<<grow, lpbx * TPLX, ldsx, s>>>(a, want);
+      } else {
+        if ((st = sse_set_lds(k_sse_row_prec<NX, false>, ldsx)) != SOFFT_OK) return st;
+        if ((st = tm.begin(SOFFT_KERNEL_SSE_ROW_PREC, s)) != SOFFT_OK) return st;
+        k_sse_row_prec<NX, false><<<grow, lpbx * TPLX, ldsx, s>>>(a, want);
+      }
       break;
   }
   SOFFT_HIP_TRY(hipGetLastError());
@@ -741,9 +808,29 @@ static sofft_status upload_doubles(DevBuf& b, const double* host, int n, hipStre
   return SOFFT_OK;
 }
 
+// The tables of the banded preconditioner of both axes into the solver's arguments.
+static sofft_status use_bands(Plan& p, SseArgs& a) {
+  sofft_status st;
+  if ((st = ensure_bands(p.ax[0])) != SOFFT_OK) return st;
+  if ((st = ensure_bands(p.ax[1])) != SOFFT_OK) return st;
+  const Axis &ax = p.ax[0], &ay = p.ax[1];
+  a.banded = 1;
+  a.bx_lam = static_cast<const cx<double>*>(ax.band_lam.p);
+  a.bx_xr = static_cast<const cx<double>*>(ax.band_xr.p);
+  a.bx_xc = static_cast<const cx<double>*>(ax.band_xc.p);
+  a.bx_start = static_cast<const int*>(ax.band_start.p);
+  a.bx_width = static_cast<const int*>(ax.band_width.p);
+  a.by_lam = static_cast<const cx<double>*>(ay.band_lam.p);
+  a.by_xr = static_cast<const cx<double>*>(ay.band_xr.p);
+  a.by_xc = static_cast<const cx<double>*>(ay.band_xc.p);
+  a.by_start = static_cast<const int*>(ay.band_start.p);
+  a.by_width = static_cast<const int*>(ay.band_width.p);
+  return SOFFT_OK;
+}
+
 sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E_host, int nE, double field,
                        void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s, LpNet* lp,
-                       int patience, const double* eta_host) {
+                       int patience, const double* eta_host, int banded) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
   SseArgs a{};
@@ -769,6 +856,7 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
     if ((st = upload_doubles(p.sse_eta, eta_host, nE, s)) != SOFFT_OK) return st;
     a.eta = static_cast<const double*>(p.sse_eta.p);
   }
+  if (banded && (st = use_bands(p, a)) != SOFFT_OK) return st;
   SseLauncher L = sse_launcher(p.ax[0].n, p.ax[1].n);
   Timing& tm = p.timing;
   const int sb = (nE + 63) / 64;
@@ -890,7 +978,8 @@ sofft_status sse_tune_shift(Plan& p, const void* f, const double* E_host, int nE
 }
 
 // w = A v (op 0) or w = P^-1 v (op 1) for one energy.
-sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s, double eta) {
+sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double field, hipStream_t s, double eta,
+                       int banded) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
   SseArgs a{};
@@ -910,6 +999,7 @@ sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double
     if ((st = upload_doubles(p.sse_eta, &eta, 1, s)) != SOFFT_OK) return st;
     a.eta = static_cast<const double*>(p.sse_eta.p);
   }
+  if (banded && (st = use_bands(p, a)) != SOFFT_OK) return st;
   CocgScalars c{};
   c.state = kActive;
   SOFFT_HIP_TRY(hipMemcpyAsync(a.sc, &c, sizeof(c), hipMemcpyHostToDevice, s));

@@ -74,6 +74,11 @@ _SIGS = {
                                                ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_sse_apply_shifted": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]),
+    "sofft_sse_solve_banded": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_double,
+                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_sse_apply_banded": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_void_p]),
     "sofft_band_tables": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_sse_tune_shift": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
@@ -237,27 +242,32 @@ class Plan:
         _check(lib().sofft_timing_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
 
-    def sse_apply(self, op, v, E, field=0.0, out=None, stream=None, eta=0.0):
+    def sse_apply(self, op, v, E, field=0.0, out=None, stream=None, eta=0.0, banded=False):
         """w = A v (op 0) or w = P^-1 v (op 1) at energy E (device tensors);
-        eta != 0 shifts the preconditioner's divisor to K - E - i eta."""
+        eta != 0 shifts the preconditioner's divisor to K - E - i eta; banded
+        selects the preconditioner of Eq. PreconFFT_ECS."""
         import torch
         ptr = _dev_ptr(v, torch.complex128, self.numel, "v")
         if out is None:
             out = torch.empty_like(v)
         optr = _dev_ptr(out, torch.complex128, self.numel, "out")
-        if eta:
+        if banded:
+            _check(lib().sofft_sse_apply_banded(self._h, int(op), ptr, optr, float(E), float(field), _stream(stream)))
+        elif eta:
             _check(lib().sofft_sse_apply_shifted(self._h, int(op), ptr, optr, float(E), float(eta), float(field),
                                                  _stream(stream)))
         else:
             _check(lib().sofft_sse_apply(self._h, int(op), ptr, optr, float(E), float(field), _stream(stream)))
         return out
 
-    def sse_solve(self, f, energies, field=0.0, rtol=1e-8, maxit=10000, out=None, stream=None, eta=None):
+    def sse_solve(self, f, energies, field=0.0, rtol=1e-8, maxit=10000, out=None, stream=None, eta=None,
+                  banded=False):
         """Solve (H - E_j) x_j = f for every energy; returns (x, stats, status).
 
         f: complex128 device tensor [ny][nx] (shared) or [nE][ny][nx].
         eta: None (the preconditioner of Eq. PreconFFT) or per-energy shifts of
-        its divisor (sofft_sse_solve_shifted)."""
+        its divisor (sofft_sse_solve_shifted).  banded: the preconditioner of
+        Eq. PreconFFT_ECS (sofft_sse_solve_banded)."""
         import torch
         E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
         nE = len(E)
@@ -267,7 +277,10 @@ class Plan:
             out = torch.empty((nE,) + self.shape, dtype=torch.complex128, device=f.device)
         optr = _dev_ptr(out, torch.complex128, nE * self.numel, "out")
         stats = (SolveStats * nE)()
-        if eta is None:
+        if banded:
+            code = lib().sofft_sse_solve_banded(self._h, fptr, per, E.ctypes.data_as(ctypes.c_void_p), nE,
+                                                float(field), optr, float(rtol), int(maxit), stats, _stream(stream))
+        elif eta is None:
             code = lib().sofft_sse_solve(self._h, fptr, per, E.ctypes.data_as(ctypes.c_void_p), nE, float(field),
                                          optr, float(rtol), int(maxit), stats, _stream(stream))
         else:

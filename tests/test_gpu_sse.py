@@ -245,3 +245,45 @@ def test_tfecs_solve_plain_and_shifted():
             assert true <= 1e-8 * (1 + 1e-3)
         print(f"   E={E}: plain {st0[j]['iterations']}, shifted {st1[j]['iterations']}", flush=True)
     plan.close()
+
+
+# ---- banded ECS eigen-preconditioner (Eq. PreconFFT_ECS)
+
+@pytest.mark.parametrize("kind,nx,ny", [("secs", 128, 96), ("tfecs", 128, 128), ("secs", 256, 128), ("tfecs", 384, 384)])
+def test_banded_preconditioner_matches_oracle(kind, nx, ny):
+    from oracle import banded as ob
+    print(f"banded P^-1 {kind} {nx}x{ny}", flush=True)
+    plan, oop, ax, ay = _setup(nx, ny, E=0.9, kind=kind)
+    rng = np.random.default_rng(nx + 7 * ny)
+    v = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    w = plan.sse_apply(1, torch.from_numpy(v).cuda(), 0.9, banded=True)
+    torch.cuda.synchronize()
+    want = ob.preconditioner(oop)(v)
+    assert rel_l2(w.cpu().numpy(), want) < 1e-12
+    plan.close()
+
+
+@pytest.mark.parametrize("kind", ["secs", "tfecs"])
+def test_banded_solve_true_residual_and_iterations(kind):
+    """COCG with the banded preconditioner reaches the oracle's true residual
+    bound, in iteration counts close to the oracle's own banded COCG."""
+    from oracle import banded as ob
+    n = 128
+    plan, _, ax, ay = _setup(n, n, kind=kind)
+    V = ot.softcore(1.0, 0.64, ax.z[None, :], ay.z[:, None])
+    fh = -wl.smooth_source(n, n, seed=1001)
+    f = torch.from_numpy(fh).cuda()
+    Es = [0.1, 1.0, 2.0]
+    _, st0, _ = plan.sse_solve(f, Es, rtol=1e-8, maxit=20000)
+    x, st, code = plan.sse_solve(f, Es, rtol=1e-8, maxit=20000, banded=True)
+    assert code == 0
+    for j, E in enumerate(Es):
+        op = osse.Operator((ax, ay), V, E)
+        true = np.linalg.norm(fh - op.matvec(x[j].cpu().numpy())) / np.linalg.norm(fh)
+        op.precond = ob.preconditioner(op)
+        _, it_o, _ = osse.cocg(op, fh, rtol=1e-8, maxit=20000)
+        print(f"   {kind} E={E}: plain {st0[j]['iterations']}, banded {st[j]['iterations']} (oracle {it_o}), "
+              f"oracle true residual {true:.2e}", flush=True)
+        assert true <= 1e-8 * (1 + 1e-3)
+        assert abs(st[j]["iterations"] - it_o) <= max(3, it_o // 20)
+    plan.close()

@@ -396,6 +396,10 @@ def test_tfecs_y_small_s_series():
     s = np.array([0.01, 0.03, 0.05])
     series = 0.5 * (8 * s ** 3 + 12 * s ** 5 + 16 * s ** 7 + 20 * s ** 9)
     assert np.max(np.abs(contour.tfecs_y(s, 0.5) / series - 1)) < 1e-9
+    # and the printed form of Eq. qTFECS, where it does not cancel
+    t = np.array([0.3, 0.6, 0.9])
+    printed = 0.5 * ((1 - t) ** -2 - (1 + t) ** -2 - 4 * t)
+    assert np.max(np.abs(contour.tfecs_y(t, 0.5) / printed - 1)) < 1e-13
 
 
 def test_tfecs_z_grows_like_the_papers_log_form():
