@@ -104,7 +104,7 @@ def gpu_tdse1d(sofft, wl, torch):
             "value": c.n * c.nsteps / wall, "unit": "grid-point-steps/s", "us_per_step": wall / c.nsteps * 1e6}
 
 
-def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0):
+def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0, extras=True):
     """Batched COCG to 1e-8 on the 512^2 stationary workload (Sec. III)."""
     c = wl.SSE_2D
     plan = sofft.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=c.theta, charge=c.charge, a2=c.a2)
@@ -124,8 +124,8 @@ def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0):
              "row_precond_dot": sofft.KERNEL_SSE_ROW_PREC}
     kern = {k: plan.timing_read(v) for k, v in kinds.items()}
     plan.timing(False)
-    shifted = pcg_shifted(plan, f, E, c.rtol, out, wall, torch)
-    band = pcg_banded(plan, f, E, c.rtol, out, wall, torch)
+    shifted = pcg_shifted(plan, f, E, c.rtol, out, wall, torch) if extras else None
+    band = pcg_banded(plan, f, E, c.rtol, out, wall, torch) if extras else None
     plan.close()
     its = np.array([s["iterations"] for s in stats])
     res = np.array([s["rel_residual"] for s in stats])
@@ -329,6 +329,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-pcg-extras", action="store_true",
+                    help="only the paper's preconditioner in the PCG leg (no shifted, banded or TFECS solves)")
     ap.add_argument("--pcg-energies", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-1d", action="store_true")
@@ -404,10 +406,11 @@ def main():
     pcg = None
     if not args.no_pcg:
         log("SSE 512^2 batched COCG to 1e-8")
-        pcg = gpu_pcg(sofft, wl, torch, args.pcg_energies)
+        pcg = gpu_pcg(sofft, wl, torch, args.pcg_energies, extras=not args.no_pcg_extras)
         log(f"  {pcg['energies']} energies in {pcg['time_to_tol_s']:.3f} s, iterations "
             f"{pcg['iterations']['min']}..{pcg['iterations']['max']} (mean {pcg['iterations']['mean']:.0f}), "
             f"{pcg['achieved_GBs_all_kernels']:.0f} GB/s over the fused passes")
+    if pcg is not None and pcg["shifted"] is not None:
         sh = pcg["shifted"]
         log(f"  shifted divisor (tuned on {sh['tuned_on']} energies): {sh['time_to_tol_s']:.3f} s "
             f"(tuning {sh['tune_s']:.3f} s), iterations mean {sh['iterations']['mean']:.0f}, "
