@@ -287,3 +287,25 @@ def test_banded_solve_true_residual_and_iterations(kind):
         assert true <= 1e-8 * (1 + 1e-3)
         assert abs(st[j]["iterations"] - it_o) <= max(3, it_o // 20)
     plan.close()
+
+
+def test_full_workload_banded_true_residual():
+    """The 512^2 x 128-energy workload with the banded ECS preconditioner:
+    every energy meets 1e-8 in fewer iterations than the plain solve needs
+    (~37.5k in total); the oracle recomputes f - A x for samples."""
+    c = wl.SSE_2D
+    print("sse full 512^2 x 128 energies, banded preconditioner", flush=True)
+    plan, oop, ax, ay = _setup(c.n, c.n, h=c.h, frac=c.R0_frac, theta=c.theta, a2=c.a2)
+    f = -wl.smooth_source(c.n, c.n, seed=0)
+    Es = c.energies()
+    x, stats, code = plan.sse_solve(torch.from_numpy(f).cuda(), Es, rtol=c.rtol, maxit=5000, banded=True)
+    assert code == 0, [s for s in stats if s["status"]][:3]
+    total = sum(s["iterations"] for s in stats)
+    print(f"   banded: {total} iterations over 128 energies", flush=True)
+    assert total < 20000
+    xs = x.cpu().numpy()
+    for j in (0, 41, 85, 127):
+        oop.E = complex(Es[j])
+        r = f - oop.matvec(xs[j])
+        assert np.linalg.norm(r) / np.linalg.norm(f) <= c.rtol * (1 + 1e-3), j
+    plan.close()
