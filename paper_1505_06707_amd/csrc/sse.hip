@@ -272,7 +272,19 @@ __device__ __forceinline__ void band_apply(cx<double> (&v)[Shape<N>::P], const L
   for (int s = 0; s < P; ++s) {
     const int n = t + TPL * s, st = start[n], w = width[n];
     cx<double> acc{0.0, 0.0};
-    for (int i = 0; i < w; ++i) acc = cfma(acc, coef[size_t(i) * N + n], L[st + i]);
+    // four entries per round, loads issued together (w <= 19: at most 5 rounds)
+    for (int i0 = 0; i0 < w; i0 += 4) {
+      cx<double> c[4], x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = min(i0 + j, w - 1);
+        c[j] = coef[size_t(i) * N + n];
+        x[j] = L[st + i];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (i0 + j < w) acc = cfma(acc, c[j], x[j]);
+    }
     v[s] = acc;
   }
   __syncthreads();
