@@ -873,8 +873,13 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
   Timing& tm = p.timing;
   const int sb = (nE + 63) / 64;
   // learned correction of z = P^-1 r for the energies in state `want`, then r^T z
+  // lp_live: some energy still iterates with the correction.  Once every
+  // iterating energy has fallen back (the host sees it when it polls), the
+  // hook and the r^T z_old term of the flexible beta are skipped: the gate
+  // would mark no energy, and beta takes the plain form for fallen-back ones.
+  bool lp_live = lp != nullptr;
   auto correct = [&](int want) -> sofft_status {
-    if (!lp) return SOFFT_OK;
+    if (!lp || !lp_live) return SOFFT_OK;
     k_sse_lp_gate<<<sb, 64, 0, s>>>(a, want);
     SOFFT_HIP_TRY(hipGetLastError());
     sofft_status q = lp_apply(*lp, a.r, a.z, nE, a.ny, a.nx, a.active, a.lp_scale, s);
@@ -916,8 +921,15 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
       if ((it + 1) % poll == 0) {
         SOFFT_HIP_TRY(hipMemcpyAsync(host.data(), a.sc, sizeof(CocgScalars) * nE, hipMemcpyDeviceToHost, s));
         SOFFT_HIP_TRY(hipStreamSynchronize(s));
-        bool any = false;
-        for (const auto& c : host) any |= c.state == kActive;
+        bool any = false, corrected = false;
+        for (const auto& c : host) {
+          any |= c.state == kActive;
+          corrected |= (c.state == kActive || c.state == kCheck) && !c.fell_back;
+        }
+        if (lp_live && !corrected) {
+          lp_live = false;
+          a.learned = 0;
+        }
         if (!any) break;
       }
     }
