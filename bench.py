@@ -190,7 +190,7 @@ def pcg_banded(plan, f, E, rtol, out, plain_s, torch):
             "max_true_rel_residual": float(max(q["rel_residual"] for q in stats)), "speedup_vs_plain": plain_s / t}
 
 
-def pcg_shifted(plan, f, E, rtol, out, plain_s, torch, candidates=(0.02, 0.05, 0.1, 0.2), every=8, probe=32):
+def pcg_shifted(plan, f, E, rtol, out, plain_s, torch, candidates=(0.02, 0.05, 0.1, 0.2), every=16, probe=24):
     """The same solve with the shifted divisor K - E - i eta (an option beside
     the paper's preconditioner): shifts tuned on every `every`-th energy by short
     batched solves, each energy taking the shift of the nearest tuned one.
