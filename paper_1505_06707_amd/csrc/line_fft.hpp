@@ -184,9 +184,23 @@ __device__ __forceinline__ void rolled_stage(cx<double> (&v)[Shape<N>::P], const
 }
 
 // In-place transform of the line held in v.  Every thread of the block must
-// call it (it contains block barriers).  The twiddles of each rolled stage are
+// call it (it contains block barriers, or wavefront barriers with WAVE).  The twiddles of each rolled stage are
 // fetched one stage ahead, so their latency hides behind the LDS exchange.
-template <typename X, int N, int SIGN>
+// Barrier between the LDS exchanges of a line: the whole block, or only the
+// wavefront (WAVE) when the caller guarantees that every line lies within one
+// wavefront, so that no exchange crosses wavefronts.
+template <bool WAVE>
+__device__ __forceinline__ void line_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <typename X, int N, int SIGN, bool WAVE = false>
 __device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, int t,
                                     const cx<double>* __restrict__ tw) {
   constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, K = Shape<N>::K;
@@ -207,10 +221,10 @@ __device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<
 #pragma unroll
       for (int m = 0; m < R0; ++m) L.template padded<PAD>(j * R0 + m) = narrow<X>(a[m]);
     }
-    __syncthreads();
+    line_sync<WAVE>();
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = widen(L.template padded<PAD>(t + TPL * s));
-    __syncthreads();
+    line_sync<WAVE>();
   }
   int off = 0;
 #pragma unroll 1
@@ -218,10 +232,10 @@ __device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<
     rolled_stage<X, N, SIGN, false>(v, L, t, w, sh);
     off += (RR - 1) * (R0 << sh);
     stage_twiddle_load<N>(w, tw + off, t, sh + LR);   // next stage
-    __syncthreads();
+    line_sync<WAVE>();
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = widen(L.template padded<PAD>(t + TPL * s));
-    __syncthreads();
+    line_sync<WAVE>();
   }
   rolled_stage<X, N, SIGN, true>(v, L, t, w, LR * (K - 1));
 }
@@ -230,7 +244,7 @@ __device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<
 // a buffer is written again only two exchanges later, after a barrier every
 // thread passed once done reading it, so the barrier that follows each read
 // is dropped; one barrier at the end leaves both buffers free for the caller.
-template <typename X, int N, int SIGN>
+template <typename X, int N, int SIGN, bool WAVE = false>
 __device__ __forceinline__ void fft2(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, const LineLDS<X>& Lb,
                                      int t, const cx<double>* __restrict__ tw) {
   constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, K = Shape<N>::K;
@@ -250,7 +264,7 @@ __device__ __forceinline__ void fft2(cx<double> (&v)[Shape<N>::P], const LineLDS
 #pragma unroll
       for (int m = 0; m < R0; ++m) L.template padded<PAD>(j * R0 + m) = narrow<X>(a[m]);
     }
-    __syncthreads();
+    line_sync<WAVE>();
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = widen(L.template padded<PAD>(t + TPL * s));
   }
@@ -262,13 +276,13 @@ __device__ __forceinline__ void fft2(cx<double> (&v)[Shape<N>::P], const LineLDS
     rolled_stage<X, N, SIGN, false>(v, Lx, t, w, sh);
     off += (RR - 1) * (R0 << sh);
     stage_twiddle_load<N>(w, tw + off, t, sh + LR);
-    __syncthreads();
+    line_sync<WAVE>();
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = widen(Lx.template padded<PAD>(t + TPL * s));
     odd = !odd;
   }
   rolled_stage<X, N, SIGN, true>(v, L, t, w, LR * (K - 1));
-  __syncthreads();
+  line_sync<WAVE>();
 }
 
 // Copy the stage twiddle tables (N entries) from global memory to LDS (all
