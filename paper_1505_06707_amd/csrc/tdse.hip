@@ -53,7 +53,8 @@ struct PassArgs {
   const double* x;        // x nodes
   const cx<double>* zx;   // z(x_j)
   const cx<double>* zy;   // z(y_j) (2D) or null
-  const cx<double>* vph;  // exp(-i V0(z) dt/2) on the grid, [ny][nx] (1D: [nx]); null when V0 = 0
+  const cx<double>* vph;  // exp(-i V0(z) dt/2) on the quadrant j < n/2 of each axis, [ny/2][nx/2]
+                          // (1D: [nx/2]); node j reads entry vfold(j, n); null when V0 = 0
   int j0, m, levels;      // ECS strip of the pass axis
   int j0y, my;            // ECS strip of the y axis (row pass of a 2D grid)
   const cx<double>* alpha;
@@ -61,6 +62,12 @@ struct PassArgs {
   const cx<double>* binv;
   int lds_line;           // LDS elements (of xch_t<T>) reserved per line
 };
+
+// The static potential is even in x and in y on every contour (z(-x) = -z(x)
+// enters V0 through z^2), so its phase table keeps one quadrant: node j of an
+// axis of n nodes reads entry min(j, n - 1 - j), the mirror node on the
+// negative side.
+__host__ __device__ __forceinline__ int vfold(int j, int n) { return j < n - 1 - j ? j : n - 1 - j; }
 
 // Crank-Nicolson on the ECS strip of a line held by the whole block (1D):
 // y = 2 B^-1 v - v by parallel cyclic reduction, staged in the line's LDS
@@ -359,10 +366,10 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     double f = 0.0;
     auto load_pot = [&]() {
       if (a.do_pot) {
-        const cx<double>* vrow = a.vph ? a.vph + size_t(crow) * N : nullptr;
+        const cx<double>* vrow = a.vph ? a.vph + size_t(vfold(crow, a.ny)) * (N / 2) : nullptr;
 #pragma unroll
         for (int s = 0; s < P; ++s) {
-          vps[s] = vrow ? vrow[t + TPL * s] : cx<double>{1.0, 0.0};
+          vps[s] = vrow ? vrow[vfold(t + TPL * s, N)] : cx<double>{1.0, 0.0};
           xs[s] = a.x[t + TPL * s];
         }
         const double* fm = run_field(a, run);
@@ -487,7 +494,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
       for (int s = 0; s < P; ++s) {
         const int e = t + TPL * s;
         const int p = strip_pos<N>(e, a.j0);
-        vps[s] = (p < m && a.vph) ? a.vph[size_t(e) * ld + ccol] : cx<double>{1.0, 0.0};
+        vps[s] = (p < m && a.vph) ? a.vph[size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)] : cx<double>{1.0, 0.0};
         if (p < m) Lc[p] = narrow<X>(v[s]);
       }
       cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln * cstride, 1}; });
@@ -549,7 +556,7 @@ __global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const
     const double fh = (a.f_mid ? a.f_mid[n] : 0.0) * a.ht;
     pot_cn_pot<T, N>(v, L, t, a, [&](int e) {
       const cx<double> ph = expi(fh * a.x[e], 0.0);
-      return a.vph ? cmul(a.vph[e], ph) : ph;
+      return a.vph ? cmul(a.vph[vfold(e, N)], ph) : ph;
     });
     const cx<double>* kin = n + 1 == nsteps ? kin_half : kin_full;
 #pragma unroll
@@ -563,12 +570,13 @@ __global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const
   for (int s = 0; s < P; ++s) a.psi[t + TPL * s] = narrow<T>(v[s]);
 }
 
-// exp(-i V0(z_x, z_y) dt/2) on the grid (the static part of the potential phase).
-__global__ void __launch_bounds__(256) k_vphase(cx<double>* out, int nx, int ny, const cx<double>* zx,
+// exp(-i V0(z_x, z_y) dt/2) (the static part of the potential phase) on the
+// quadrant [hy][hx] of nodes j < n/2 per axis (hy = 1 in 1D).
+__global__ void __launch_bounds__(256) k_vphase(cx<double>* out, int hx, int hy, const cx<double>* zx,
                                                 const cx<double>* zy, double charge, double a2, double ht) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= size_t(nx) * ny) return;
-  const int jx = int(i % nx), jy = int(i / nx);
+  if (i >= size_t(hx) * hy) return;
+  const int jx = int(i % hx), jy = int(i / hx);
   const cx<double> zy2 = zy ? cmul(zy[jy], zy[jy]) : cx<double>{0.0, 0.0};   // 1D: no y term
   out[i] = potential_phase(cmul(zx[jx], zx[jx]) + zy2 + cx<double>{a2, 0.0}, charge, 0.0, ht);
 }
@@ -823,8 +831,8 @@ static sofft_status occupancy_n(bool row, int n, int lds_line, int threads, int*
 sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
   if (changed) *changed = false;
   if (p.prob.charge == 0.0 || p.vphase_ht == 0.5 * dt) return SOFFT_OK;
-  const int nx = int(p.ax[0].n), ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
-  const size_t bytes = size_t(nx) * ny * sizeof(cx<double>);
+  const int hx = int(p.ax[0].n) / 2, hy = p.prob.ndim == 2 ? int(p.ax[1].n) / 2 : 1;
+  const size_t bytes = size_t(hx) * hy * sizeof(cx<double>);
   if (!p.vphase.p) {
     if (hipMalloc(&p.vphase.p, bytes) != hipSuccess) {
       p.vphase.p = nullptr;
@@ -833,8 +841,8 @@ sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
     }
     p.vphase.bytes = bytes;
   }
-  const size_t n = size_t(nx) * ny;
-  k_vphase<<<unsigned((n + 255) / 256), 256, 0, s>>>(static_cast<cx<double>*>(p.vphase.p), nx, ny,
+  const size_t n = size_t(hx) * hy;
+  k_vphase<<<unsigned((n + 255) / 256), 256, 0, s>>>(static_cast<cx<double>*>(p.vphase.p), hx, hy,
                                                      static_cast<const cx<double>*>(p.ax[0].z_dev.p),
                                                      p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p)
                                                                       : nullptr,
