@@ -12,7 +12,7 @@ import pytest
 
 from oracle import tdse as ot
 from paper_1505_06707_amd import workloads as wl
-from tests.helpers import oracle_axis, rel_l2
+from tests.helpers import CONTOURS, oracle_axis, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -185,3 +185,42 @@ def test_full_batch_workload_sampled():
         single = _single_run(n, s.C64, psi0[r], f[r], dt)
         assert np.array_equal(out[r], single), f"run {r} (n={n}) differs from the single-grid path"
         print(f"   run {r} n={n}: equal to the single-grid path", flush=True)
+
+
+
+def test_batch_mixed_contours_with_tfecs():
+    """Runs with the SECS and the TFECS contour (different problem statements,
+    hence different classes, even at the same shape) advanced by one batch:
+    each run equals its single-grid propagation bit for bit and the oracle."""
+    s = _sofft()
+    specs = [(64, "secs"), (64, "tfecs"), (96, "tfecs")]
+    dt, nsteps = 0.05, 40
+    problems, psi0, fs = [], [], []
+    for i, (n, kind) in enumerate(specs):
+        L = n * 0.2
+        problems.append(s.problem([n, n], [L, L], R0=[0.8 * L / 2] * 2, theta=0.5, contour=CONTOURS[kind][1],
+                                  charge=1.0, a2=0.64, dtype=s.C128))
+        x = ot.Axis(n, L).x
+        psi0.append(wl.gaussian_2d(x, x, **wl.packet_params(20 + i)))
+        fs.append(wl.Pulse(E0=0.05, omega=0.3, cycles=2).at_midpoints(0.0, dt, nsteps))
+    print("batch with SECS and TFECS runs", flush=True)
+    b = s.Batch(problems)
+    states = [torch.from_numpy(p.astype(np.complex128)).cuda() for p in psi0]
+    b.propagate(states, dt, nsteps, torch.from_numpy(np.stack(fs)).cuda())
+    torch.cuda.synchronize()
+    out = [t.cpu().numpy() for t in states]
+    b.close()
+    for i, (n, kind) in enumerate(specs):
+        L = n * 0.2
+        plan = s.Plan([n, n], [L, L], R0=[0.8 * L / 2] * 2, theta=0.5, contour=CONTOURS[kind][1], charge=1.0, a2=0.64)
+        psi = torch.from_numpy(psi0[i].astype(np.complex128)).cuda()
+        plan.propagate(psi, dt, nsteps, torch.from_numpy(fs[i]).cuda())
+        torch.cuda.synchronize()
+        single = psi.cpu().numpy()
+        plan.close()
+        assert np.array_equal(out[i], single), f"run {i} ({kind}) differs from the single-grid path"
+        ax = oracle_axis(n, L, 0.8 * L / 2, 0.5, kind)
+        o = ot.Problem2D(ax, ax, Zc=1.0, a2=0.64).propagate(psi0[i], dt, fs[i])
+        err = rel_l2(out[i], o)
+        print(f"   run {i} n={n} {kind}: rel L2 vs oracle {err:.2e}", flush=True)
+        assert err < TOL64

@@ -193,6 +193,24 @@ def test_norm2_and_zero_steps():
 TOL32 = 1e-5
 
 
+def test_fp32_2d_tfecs_against_fp64_oracle():
+    """complex64 state on the TFECS contour (large |q| near the box edges)."""
+    from paper_1505_06707_amd import sofft
+    print("2D c64 TFECS 128^2 x 1000", flush=True)
+    n, h = 128, 0.2
+    L = n * h
+    R0 = 0.7 * L / 2
+    ax = ot.Axis(n, L, R0=R0)
+    psi0 = wl.gaussian_2d(ax.x, ax.x, x0=0.3, y0=-0.2, px=1.5, py=1.0)
+    f = wl.Pulse().at_midpoints(0.0, 0.05, 1000)
+    args = (n, n, L, L, R0, R0, 0.5, "tfecs", 1.0, 0.64, psi0, 0.05, f)
+    g = run_gpu_2d(*args, dtype=sofft.C64)
+    o = oracle_2d(*args)
+    err = rel_l2(g, o)
+    print(f"   rel L2 (c64 vs FP64 oracle) = {err:.3e}", flush=True)
+    assert err < TOL32
+
+
 @pytest.mark.parametrize("n,steps", [(128, 2000), (256, 500)])
 def test_fp32_2d_error_against_fp64_oracle(n, steps):
     from paper_1505_06707_amd import sofft
