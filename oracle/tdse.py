@@ -66,12 +66,16 @@ def softcore(Zc, a2, *zs):
 
 
 class Problem1D:
-    def __init__(self, axis, Zc=1.0, a2=2.0):
+    """U(x, t) = V0 + f(t) W: by default the soft-core V0 at z(x) and W = x;
+    ``V0`` (complex, at z) and ``W`` (real) on the grid replace them."""
+
+    def __init__(self, axis, Zc=1.0, a2=2.0, V0=None, W=None):
         self.ax = axis
-        self.V0 = softcore(Zc, a2, axis.z)
+        self.V0 = softcore(Zc, a2, axis.z) if V0 is None else np.asarray(V0, dtype=complex)
+        self.W = axis.x if W is None else np.asarray(W, dtype=float)
 
     def potential(self, f):
-        return self.V0 + f * self.ax.x
+        return self.V0 + f * self.W
 
     def step(self, psi, tau, f_mid):
         ax = self.ax
@@ -92,13 +96,18 @@ class Problem1D:
 
 
 class Problem2D:
-    def __init__(self, axis_x, axis_y, Zc=1.0, a2=0.64):
+    """U = V0 + f(t) W on the [ny][nx] grid: by default the soft-core V0 at
+    (z_x, z_y) and W = x; ``V0`` (complex) and ``W`` (real) replace them."""
+
+    def __init__(self, axis_x, axis_y, Zc=1.0, a2=0.64, V0=None, W=None):
         self.ax, self.ay = axis_x, axis_y
-        self.V0 = softcore(Zc, a2, axis_x.z[None, :], axis_y.z[:, None])
+        self.V0 = (softcore(Zc, a2, axis_x.z[None, :], axis_y.z[:, None]) if V0 is None
+                   else np.asarray(V0, dtype=complex))
+        self.W = np.broadcast_to(axis_x.x[None, :], self.V0.shape) if W is None else np.asarray(W, dtype=float)
         self.K = (axis_x.k[None, :] ** 2 + axis_y.k[:, None] ** 2) / 2
 
     def potential(self, f):
-        return self.V0 + f * self.ax.x[None, :]
+        return self.V0 + f * self.W
 
     def _kinetic(self, psi, phase):
         ax, ay = self.ax, self.ay

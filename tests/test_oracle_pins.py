@@ -437,3 +437,30 @@ def test_tfecs_box_edge_decouples_the_scaled_stencil():
     c = 1.0 / (2 * ax.h ** 2)
     assert C[n - 1, 0] == c and C[0, n - 1] == c
     assert np.all(np.isfinite(C))
+
+
+# ---- caller-supplied potential U = V0 + f(t) W on the grid
+
+def test_constant_user_potential_adds_a_global_phase():
+    """V0 = c (constant), W = 0: exp(-iUt) commutes with everything, so the
+    state is the free one times exp(-i c t)."""
+    ax, ay = _axis(64, 25.6, kind=contour.OFF, R0=8.0), _axis(48, 19.2, kind=contour.OFF, R0=6.0)
+    psi0 = cf.free_gaussian(ax.x, 0.0, 0.5, 0.7)[None, :] * cf.free_gaussian(ay.x, 0.0, -0.3, 0.2)[:, None]
+    c, tau, nst = 0.37 - 0.0j, 0.05, 40
+    free = tdse.Problem2D(ax, ay, Zc=0.0).propagate(psi0, tau, np.zeros(nst))
+    got = tdse.Problem2D(ax, ay, V0=np.full((48, 64), c), W=np.zeros((48, 64))).propagate(psi0, tau, np.zeros(nst))
+    assert np.max(np.abs(got - free * np.exp(-1j * c * tau * nst))) < 1e-12
+
+
+def test_uniform_field_along_y_shifts_the_mean_momentum():
+    """U = f y (W = y, V0 = 0): by Ehrenfest d<p_y>/dt = -f exactly, while the
+    packet stays away from the box edges."""
+    ax, ay = _axis(64, 38.4, kind=contour.OFF, R0=8.0), _axis(64, 38.4, kind=contour.OFF, R0=8.0)
+    psi0 = cf.free_gaussian(ax.x, 0.0, 0.0, 0.0)[None, :] * cf.free_gaussian(ay.x, 0.0, 0.0, 0.0)[:, None]
+    f, tau, nst = 0.2, 0.02, 100
+    prob = tdse.Problem2D(ax, ay, V0=np.zeros((64, 64)), W=np.broadcast_to(ay.x[:, None], (64, 64)))
+    psi = prob.propagate(psi0, tau, np.full(nst, f))
+    spec = np.fft.fft(psi, axis=0)
+    ky = 2 * np.pi * np.fft.fftfreq(64, d=ay.h)
+    py = np.sum(ky[:, None] * np.abs(spec) ** 2) / np.sum(np.abs(spec) ** 2)
+    assert abs(py - (-f * tau * nst)) < 1e-10
