@@ -101,6 +101,30 @@ sofft_status sofft_grid_nodes(const sofft_plan* plan, int32_t axis, double* x_ho
  * remainder C has a non-zero row (0 when ECS is off). */
 sofft_status sofft_strip_length(const sofft_plan* plan, int32_t axis, int64_t* m);
 
+/* Replace the potential of the plan by U(x, t) = V0(x) + f(t) W(x) (the
+ * general U(z(x), t) of Sec. II, Eq. TDSE, with a dipole-like time dependence):
+ *   v0  device, complex128 [n_y][n_x] (interleaved re, im), V0 already evaluated
+ *       at the complex coordinates z(x) of the contour; NULL: the problem's
+ *       soft-core (charge, a2)
+ *   w   device, double [n_y][n_x], real; NULL: W = x (polarisation along x)
+ * Both stay owned by the caller and are read, not copied: they must stay
+ * valid, and unchanged, while propagations and solves on the plan use them
+ * (W is read at every step; the phase table exp(-i V0 dt/2) is rebuilt from
+ * V0 at the next propagation, or for a new dt).  Call again after changing
+ * V0.  Applies to sofft_propagate and the sofft_sse_* solves and applications
+ * (whose U is V0 + field W).  Takes effect for work enqueued after the call;
+ * work already enqueued still reads the previous buffers, which must stay
+ * valid until it finishes.  sofft_set_potential(plan, NULL, NULL) restores the
+ * problem's potential.  Returns SOFFT_EINVAL for a NULL plan. */
+sofft_status sofft_set_potential(sofft_plan* plan, const void* v0, const double* w);
+
+/* Write the soft-core V0 = -charge / sqrt(z_x^2 [+ z_y^2] + a2) (principal
+ * branch) on the plan's grid, at the contour coordinates z, into v0 (device,
+ * complex128 [n_y][n_x]; caller-owned).  A helper for sofft_set_potential:
+ * scale, shift or add to it before passing it there.  charge and a2 finite,
+ * a2 > 0 unless charge = 0.  Asynchronous on the stream. */
+sofft_status sofft_make_softcore(const sofft_plan* plan, double charge, double a2, void* v0, void* stream);
+
 /* Advance psi (device, in place, n_x [* n_y] elements) by nsteps split-operator
  * steps of length dt (Sec. II):
  *   psi <- F^-1 e^{-iK dt/2} F  e^{-iU dt/2}  e^{-iC dt}  e^{-iU dt/2}  F^-1 e^{-iK dt/2} F  psi

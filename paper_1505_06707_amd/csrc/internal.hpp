@@ -97,6 +97,11 @@ struct Plan {
   // exp(-i V0 dt/2) on the grid for the dt in vphase_ht = dt/2 (NaN: none)
   DevBuf vphase;
   double vphase_ht = __builtin_nan("");
+  // A caller's potential U = V0 + f W (device, caller-owned): V0 complex
+  // [ny][nx] in place of the soft-core, W real [ny][nx] in place of x; null:
+  // the problem's own.
+  const void* user_v0 = nullptr;
+  const double* user_w = nullptr;
 };
 
 // Table builders (plan.hip).
@@ -139,6 +144,8 @@ sofft_status launch_propagate_1d(Plan& p, void* psi, double dt, int64_t nsteps, 
 sofft_status launch_propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
                                  hipStream_t s);
 sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s);
+// V0 = -charge / sqrt(sum z^2 + a2) on the plan's grid into out (complex, [ny][nx]).
+sofft_status launch_softcore(const Plan& p, double charge, double a2, void* out, hipStream_t s);
 sofft_status launch_pass(Plan& p, const PassRequest& rq, hipStream_t s);
 // Build or refresh the potential-phase table of a plan for dt (enqueued on s).
 sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed);

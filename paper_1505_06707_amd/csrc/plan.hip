@@ -494,6 +494,25 @@ sofft_status sofft_propagate(sofft_plan* plan, void* psi, double dt, int64_t nst
                               : launch_propagate_2d(*plan, psi, dt, nsteps, f_mid, s);
 }
 
+sofft_status sofft_set_potential(sofft_plan* plan, const void* v0, const double* w) {
+  if (!plan) {
+    set_error("bad argument to sofft_set_potential");
+    return SOFFT_EINVAL;
+  }
+  plan->user_v0 = v0;
+  plan->user_w = w;
+  plan->vphase_ht = __builtin_nan("");   // the phase table follows V0
+  return SOFFT_OK;
+}
+
+sofft_status sofft_make_softcore(const sofft_plan* plan, double charge, double a2, void* v0, void* stream) {
+  if (!plan || !v0 || !std::isfinite(charge) || !std::isfinite(a2) || (charge != 0.0 && !(a2 > 0))) {
+    set_error("bad argument to sofft_make_softcore");
+    return SOFFT_EINVAL;
+  }
+  return launch_softcore(*plan, charge, a2, v0, reinterpret_cast<hipStream_t>(stream));
+}
+
 sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
                              int32_t nE, double field, void* x_out, double rtol, int32_t maxit,
                              sofft_solve_stats* stats, void* stream) {

@@ -599,14 +599,21 @@ __global__ void k_sse_true(SseArgs a, double rtol, int maxit) {
   }
 }
 
-// U on the grid: soft-core at (z_x, z_y) plus field * x.
+// U on the grid: soft-core at (z_x, z_y) plus field * x, or a caller's V0
+// (v0 non-null) and W (w non-null) in their places.
 __global__ void k_sse_potential(cx<double>* V, int nx, int ny, const cx<double>* zx, const cx<double>* zy,
-                                const double* x, double charge, double a2, double field) {
+                                const double* x, double charge, double a2, double field, const cx<double>* v0,
+                                const double* w) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= size_t(nx) * ny) return;
   const int jx = int(i % nx), jy = int(i / nx);
+  const double fw = field * (w ? w[i] : x[jx]);
+  if (v0) {
+    V[i] = v0[i] + cx<double>{fw, 0.0};
+    return;
+  }
   const cx<double> s = cmul(zx[jx], zx[jx]) + cmul(zy[jy], zy[jy]) + cx<double>{a2, 0.0};
-  V[i] = potential_value(s, charge, field * x[jx]);
+  V[i] = potential_value(s, charge, fw);
 }
 
 // ---------------------------------------------------------------- host side
@@ -787,7 +794,8 @@ static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipSt
   const int threads = 256;
   k_sse_potential<<<int((vec + threads - 1) / threads), threads, 0, s>>>(
       V, a.nx, a.ny, static_cast<const cx<double>*>(X.z_dev.p), static_cast<const cx<double>*>(Y.z_dev.p),
-      static_cast<const double*>(X.x_dev.p), p.prob.charge, p.prob.a2, field);
+      static_cast<const double*>(X.x_dev.p), p.prob.charge, p.prob.a2, field,
+      static_cast<const cx<double>*>(p.user_v0), p.user_w);
   SOFFT_HIP_TRY(hipGetLastError());
   return SOFFT_OK;
 }

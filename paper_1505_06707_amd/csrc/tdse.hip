@@ -55,6 +55,8 @@ struct PassArgs {
   const cx<double>* zy;   // z(y_j) (2D) or null
   const cx<double>* vph;  // exp(-i V0(z) dt/2) on the quadrant j < n/2 of each axis, [ny/2][nx/2]
                           // (1D: [nx/2]); node j reads entry vfold(j, n); null when V0 = 0
+  int vfull;              // vph holds the whole grid, [ny][nx] (a caller's V0, no symmetry)
+  const double* w;        // W of the field term f W on the grid, [ny][nx]; null: W = x
   int j0, m, levels;      // ECS strip of the pass axis
   int j0y, my;            // ECS strip of the y axis (row pass of a 2D grid)
   const cx<double>* alpha;
@@ -366,11 +368,14 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     double f = 0.0;
     auto load_pot = [&]() {
       if (a.do_pot) {
-        const cx<double>* vrow = a.vph ? a.vph + size_t(vfold(crow, a.ny)) * (N / 2) : nullptr;
+        const cx<double>* vrow =
+            a.vph ? a.vph + (a.vfull ? size_t(crow) * N : size_t(vfold(crow, a.ny)) * (N / 2)) : nullptr;
+        const double* wrow = a.w ? a.w + size_t(crow) * N : a.x;
 #pragma unroll
         for (int s = 0; s < P; ++s) {
-          vps[s] = vrow ? vrow[vfold(t + TPL * s, N)] : cx<double>{1.0, 0.0};
-          xs[s] = a.x[t + TPL * s];
+          const int e = t + TPL * s;
+          vps[s] = vrow ? vrow[a.vfull ? e : vfold(e, N)] : cx<double>{1.0, 0.0};
+          xs[s] = wrow[e];
         }
         const double* fm = run_field(a, run);
         f = fm ? fm[step] : 0.0;
@@ -482,7 +487,9 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
       // C_y and the second potential half-step, on the y-strip only.
       const double* fm = run_field(a, run);
       const double f = fm ? fm[step] : 0.0;
-      const cx<double> lph = expi(f * a.x[ccol] * a.ht, 0.0);   // exp(-i f x dt/2)
+      // exp(-i f x dt/2), the same along the column (W = x); with a caller's W
+      // the phase is taken per node below and lph is 1
+      const cx<double> lph = a.w ? cx<double>{1.0, 0.0} : expi(f * a.x[ccol] * a.ht, 0.0);
       const int m = a.m;
       // The strips go to a contiguous area per column (odd stride 2m + 1), not
       // the interleaved FFT layout: one wavefront's positions are then
@@ -494,7 +501,10 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
       for (int s = 0; s < P; ++s) {
         const int e = t + TPL * s;
         const int p = strip_pos<N>(e, a.j0);
-        vps[s] = (p < m && a.vph) ? a.vph[size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)] : cx<double>{1.0, 0.0};
+        vps[s] = (p < m && a.vph) ? a.vph[a.vfull ? size_t(e) * ld + ccol
+                                                  : size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)]
+                                  : cx<double>{1.0, 0.0};
+        if (p < m && a.w) vps[s] = cmul(vps[s], expi(f * a.w[size_t(e) * ld + ccol] * a.ht, 0.0));
         if (p < m) Lc[p] = narrow<X>(v[s]);
       }
       cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln * cstride, 1}; });
@@ -555,8 +565,8 @@ __global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const
   for (int64_t n = 0; n < nsteps; ++n) {
     const double fh = (a.f_mid ? a.f_mid[n] : 0.0) * a.ht;
     pot_cn_pot<T, N>(v, L, t, a, [&](int e) {
-      const cx<double> ph = expi(fh * a.x[e], 0.0);
-      return a.vph ? cmul(a.vph[vfold(e, N)], ph) : ph;
+      const cx<double> ph = expi(fh * (a.w ? a.w[e] : a.x[e]), 0.0);
+      return a.vph ? cmul(a.vph[a.vfull ? e : vfold(e, N)], ph) : ph;
     });
     const cx<double>* kin = n + 1 == nsteps ? kin_half : kin_full;
 #pragma unroll
@@ -579,6 +589,24 @@ __global__ void __launch_bounds__(256) k_vphase(cx<double>* out, int hx, int hy,
   const int jx = int(i % hx), jy = int(i / hx);
   const cx<double> zy2 = zy ? cmul(zy[jy], zy[jy]) : cx<double>{0.0, 0.0};   // 1D: no y term
   out[i] = potential_phase(cmul(zx[jx], zx[jx]) + zy2 + cx<double>{a2, 0.0}, charge, 0.0, ht);
+}
+
+// exp(-i V0 dt/2) from a caller's V0 on the whole grid (n nodes).
+__global__ void __launch_bounds__(256) k_vphase_user(cx<double>* out, const cx<double>* v0, size_t n, double ht) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const cx<double> v = v0[i];
+  out[i] = expi(v.re * ht, v.im * ht);
+}
+
+// The soft-core V0 = -charge / sqrt(z_x^2 [+ z_y^2] + a2) on the [ny][nx] grid.
+__global__ void __launch_bounds__(256) k_softcore(cx<double>* out, int nx, int ny, const cx<double>* zx,
+                                                  const cx<double>* zy, double charge, double a2) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= size_t(nx) * ny) return;
+  const int jx = int(i % nx), jy = int(i / nx);
+  const cx<double> zy2 = zy ? cmul(zy[jy], zy[jy]) : cx<double>{0.0, 0.0};
+  out[i] = potential_value(cmul(zx[jx], zx[jx]) + zy2 + cx<double>{a2, 0.0}, charge, 0.0);
 }
 
 __global__ void k_step_add(int64_t* counter, int64_t delta, int set) {
@@ -654,6 +682,8 @@ static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   a.zx = static_cast<const cx<double>*>(p.ax[0].z_dev.p);
   a.zy = p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p) : nullptr;
   a.vph = p.vphase_ht == 0.5 * dt ? static_cast<const cx<double>*>(p.vphase.p) : nullptr;
+  a.vfull = p.user_v0 != nullptr;
+  a.w = p.user_w;
   a.j0 = int(A.j0);
   a.m = int(A.m);
   a.levels = A.levels;
@@ -827,12 +857,17 @@ static sofft_status occupancy_n(bool row, int n, int lds_line, int threads, int*
   return SOFFT_EUNSUPPORTED;
 }
 
-// The table of exp(-i V0 dt/2) for this dt (plans with a potential).
+// The table of exp(-i V0 dt/2) for this dt (plans with a potential): one
+// quadrant for the soft-core, the whole grid for a caller's V0.
 sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
   if (changed) *changed = false;
-  if (p.prob.charge == 0.0 || p.vphase_ht == 0.5 * dt) return SOFFT_OK;
-  const int hx = int(p.ax[0].n) / 2, hy = p.prob.ndim == 2 ? int(p.ax[1].n) / 2 : 1;
-  const size_t bytes = size_t(hx) * hy * sizeof(cx<double>);
+  if ((p.prob.charge == 0.0 && !p.user_v0) || p.vphase_ht == 0.5 * dt) return SOFFT_OK;
+  const bool full = p.user_v0 != nullptr;
+  const int ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
+  const int hx = int(p.ax[0].n) / 2, hy = p.prob.ndim == 2 ? ny / 2 : 1;
+  const size_t n = full ? size_t(p.ax[0].n) * ny : size_t(hx) * hy;
+  const size_t bytes = n * sizeof(cx<double>);
+  if (p.vphase.p && p.vphase.bytes < bytes) dev_free(p.vphase);
   if (!p.vphase.p) {
     if (hipMalloc(&p.vphase.p, bytes) != hipSuccess) {
       p.vphase.p = nullptr;
@@ -841,7 +876,14 @@ sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
     }
     p.vphase.bytes = bytes;
   }
-  const size_t n = size_t(hx) * hy;
+  if (full) {
+    k_vphase_user<<<unsigned((n + 255) / 256), 256, 0, s>>>(static_cast<cx<double>*>(p.vphase.p),
+                                                          static_cast<const cx<double>*>(p.user_v0), n, 0.5 * dt);
+    SOFFT_HIP_TRY(hipGetLastError());
+    p.vphase_ht = 0.5 * dt;
+    if (changed) *changed = true;
+    return SOFFT_OK;
+  }
   k_vphase<<<unsigned((n + 255) / 256), 256, 0, s>>>(static_cast<cx<double>*>(p.vphase.p), hx, hy,
                                                      static_cast<const cx<double>*>(p.ax[0].z_dev.p),
                                                      p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p)
@@ -992,6 +1034,16 @@ sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s) 
   double acc = 0.0;
   for (int b = 0; b < blocks; ++b) acc += p.host_partials[b];
   *out = acc;
+  return SOFFT_OK;
+}
+
+sofft_status launch_softcore(const Plan& p, double charge, double a2, void* out, hipStream_t s) {
+  const int nx = int(p.ax[0].n), ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
+  const size_t n = size_t(nx) * ny;
+  k_softcore<<<unsigned((n + 255) / 256), 256, 0, s>>>(
+      static_cast<cx<double>*>(out), nx, ny, static_cast<const cx<double>*>(p.ax[0].z_dev.p),
+      p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p) : nullptr, charge, a2);
+  SOFFT_HIP_TRY(hipGetLastError());
   return SOFFT_OK;
 }
 

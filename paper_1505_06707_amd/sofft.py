@@ -64,6 +64,9 @@ _SIGS = {
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_norm2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.c_void_p]),
+    "sofft_set_potential": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_make_softcore": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
     "sofft_sse_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_double,
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
@@ -230,6 +233,25 @@ class Plan:
         fptr = ctypes.c_void_p(0) if f_mid is None else _dev_ptr(f_mid, torch.float64, nsteps, "f_mid")
         _check(lib().sofft_propagate(self._h, ptr, float(dt), int(nsteps), fptr, _stream(stream)))
         return psi
+
+    def set_potential(self, V0=None, W=None):
+        """U = V0 + f(t) W on the grid (device tensors [ny][nx]: V0 complex128 at
+        z(x), W float64); None keeps the problem's soft-core V0 / W = x.  The
+        plan holds references to both, as the library reads them in place."""
+        import torch
+        v0 = ctypes.c_void_p(0) if V0 is None else _dev_ptr(V0, torch.complex128, self.numel, "V0")
+        w = ctypes.c_void_p(0) if W is None else _dev_ptr(W, torch.float64, self.numel, "W")
+        _check(lib().sofft_set_potential(self._h, v0, w))
+        self._user_potential = (V0, W)
+
+    def make_softcore(self, charge=1.0, a2=2.0, out=None, stream=None):
+        """V0 = -charge / sqrt(sum z^2 + a2) on the grid (complex128 device tensor)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.complex128, device="cuda")
+        ptr = _dev_ptr(out, torch.complex128, self.numel, "out")
+        _check(lib().sofft_make_softcore(self._h, float(charge), float(a2), ptr, _stream(stream)))
+        return out
 
     def timing(self, enable=True):
         """Enable (clearing the record) or disable per-launch event timing."""

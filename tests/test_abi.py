@@ -68,3 +68,5 @@ def test_null_arguments_are_rejected():
     assert L.sofft_plan_create(None, None) == -1
     assert L.sofft_propagate(None, None, 0.05, 1, None, None) == -1
     assert L.sofft_norm2(None, None, None, None) == -1
+    assert L.sofft_set_potential(None, None, None) == -1
+    assert L.sofft_make_softcore(None, 1.0, 1.0, None, None) == -1
