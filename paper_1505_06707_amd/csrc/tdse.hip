@@ -331,7 +331,9 @@ __device__ __forceinline__ void run_tiles(int ntiles, Body& body) {
 // Block LDS layout of the 2D passes: [line 0][line 1]...; a block holds
 // blockDim.x / TPL lines of a.lds_line elements.  FFT twiddles and CN
 // coefficients are read from global memory (they stay in the vector L1).
-template <typename T, int N, bool PERSIST>
+// UP: the plan carries a caller's potential (a whole-grid V0 table and/or W
+// in place of x); the other instantiations keep the soft-core path alone.
+template <typename T, int N, bool PERSIST, bool UP = false>
 __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (kernel_waves<N, PERSIST>())) k_row_pass(PassArgs<T> a) {
   using X = xch_t<T>;
   constexpr bool park = std::is_same<X, double>::value;
@@ -368,14 +370,23 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     double f = 0.0;
     auto load_pot = [&]() {
       if (a.do_pot) {
-        const cx<double>* vrow =
-            a.vph ? a.vph + (a.vfull ? size_t(crow) * N : size_t(vfold(crow, a.ny)) * (N / 2)) : nullptr;
-        const double* wrow = a.w ? a.w + size_t(crow) * N : a.x;
+        if constexpr (UP) {
+          const cx<double>* vrow =
+              a.vph ? a.vph + (a.vfull ? size_t(crow) * N : size_t(vfold(crow, a.ny)) * (N / 2)) : nullptr;
+          const double* wrow = a.w ? a.w + size_t(crow) * N : a.x;
 #pragma unroll
-        for (int s = 0; s < P; ++s) {
-          const int e = t + TPL * s;
-          vps[s] = vrow ? vrow[a.vfull ? e : vfold(e, N)] : cx<double>{1.0, 0.0};
-          xs[s] = wrow[e];
+          for (int s = 0; s < P; ++s) {
+            const int e = t + TPL * s;
+            vps[s] = vrow ? vrow[a.vfull ? e : vfold(e, N)] : cx<double>{1.0, 0.0};
+            xs[s] = wrow[e];
+          }
+        } else {
+          const cx<double>* vrow = a.vph ? a.vph + size_t(vfold(crow, a.ny)) * (N / 2) : nullptr;
+#pragma unroll
+          for (int s = 0; s < P; ++s) {
+            vps[s] = vrow ? vrow[vfold(t + TPL * s, N)] : cx<double>{1.0, 0.0};
+            xs[s] = a.x[t + TPL * s];
+          }
         }
         const double* fm = run_field(a, run);
         f = fm ? fm[step] : 0.0;
@@ -461,7 +472,7 @@ __device__ __forceinline__ int xcd_block(int b, int nblk) {
   return (b % 8) * (nblk / 8) + b / 8;
 }
 
-template <typename T, int N, bool PERSIST>
+template <typename T, int N, bool PERSIST, bool UP = false>
 __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (kernel_waves<N, PERSIST>())) k_col_pass(PassArgs<T> a) {
   using X = xch_t<T>;
   constexpr int P = Shape<N>::P, TPL = N / P;
@@ -489,7 +500,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
       const double f = fm ? fm[step] : 0.0;
       // exp(-i f x dt/2), the same along the column (W = x); with a caller's W
       // the phase is taken per node below and lph is 1
-      const cx<double> lph = a.w ? cx<double>{1.0, 0.0} : expi(f * a.x[ccol] * a.ht, 0.0);
+      const cx<double> lph = (UP && a.w) ? cx<double>{1.0, 0.0} : expi(f * a.x[ccol] * a.ht, 0.0);
       const int m = a.m;
       // The strips go to a contiguous area per column (odd stride 2m + 1), not
       // the interleaved FFT layout: one wavefront's positions are then
@@ -501,10 +512,14 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
       for (int s = 0; s < P; ++s) {
         const int e = t + TPL * s;
         const int p = strip_pos<N>(e, a.j0);
-        vps[s] = (p < m && a.vph) ? a.vph[a.vfull ? size_t(e) * ld + ccol
-                                                  : size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)]
-                                  : cx<double>{1.0, 0.0};
-        if (p < m && a.w) vps[s] = cmul(vps[s], expi(f * a.w[size_t(e) * ld + ccol] * a.ht, 0.0));
+        if constexpr (UP) {
+          vps[s] = (p < m && a.vph) ? a.vph[a.vfull ? size_t(e) * ld + ccol
+                                                    : size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)]
+                                    : cx<double>{1.0, 0.0};
+          if (p < m && a.w) vps[s] = cmul(vps[s], expi(f * a.w[size_t(e) * ld + ccol] * a.ht, 0.0));
+        } else {
+          vps[s] = (p < m && a.vph) ? a.vph[size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)] : cx<double>{1.0, 0.0};
+        }
         if (p < m) Lc[p] = narrow<X>(v[s]);
       }
       cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln * cstride, 1}; });
@@ -755,6 +770,8 @@ template <typename T, int N, bool ROW>
 static sofft_status pass_set_lds(size_t lds) {
   sofft_status st = ROW ? set_lds(k_row_pass<T, N, false>, lds) : set_lds(k_col_pass<T, N, false>, lds);
   if (st == SOFFT_OK) st = ROW ? set_lds(k_row_pass<T, N, true>, lds) : set_lds(k_col_pass<T, N, true>, lds);
+  if (st == SOFFT_OK)
+    st = ROW ? set_lds(k_row_pass<T, N, false, true>, lds) : set_lds(k_col_pass<T, N, false, true>, lds);
   return st;
 }
 
@@ -778,10 +795,17 @@ static sofft_status pass(PassArgs<T> a, PassLaunch cfg, hipStream_t s, Timing* t
   if (st != SOFFT_OK) return st;
   const int lines = a.nruns * (ROW ? a.ny : a.nx);
   a.ntiles = (lines + lpb - 1) / lpb;
-  const bool persist = want_persist && cfg.grid < a.ntiles;
+  // a caller's potential (single plans only) takes the one-block-per-tile grid
+  const bool user = a.vfull || a.w;
+  const bool persist = !user && want_persist && cfg.grid < a.ntiles;
   const int blocks = persist ? cfg.grid : a.ntiles;
   if (tm && (st = tm->begin(ROW ? SOFFT_KERNEL_ROW : SOFFT_KERNEL_COL, s)) != SOFFT_OK) return st;
-  if (ROW) {
+  if (user) {
+    if (ROW)
+      k_row_pass<T, N, false, true><<<blocks, lpb * TPL, lds, s>>>(a);
+    else
+      k_col_pass<T, N, false, true><<<blocks, lpb * TPL, lds, s>>>(a);
+  } else if (ROW) {
     if (persist)
       k_row_pass<T, N, true><<<blocks, lpb * TPL, lds, s>>>(a);
     else
