@@ -157,7 +157,10 @@ typedef struct {
  * static potential of the plan plus field * x (field = 0 after a pulse).
  * Iterations stop when ||r|| / ||f|| <= rtol (Hermitian 2-norm of the
  * recurrence residual); the residual is then recomputed as f - A x and the
- * iteration restarts from it while that exceeds rtol.
+ * iteration restarts from it while that exceeds rtol.  The same restart is
+ * taken when the recurrence residual has made no new minimum for 2000
+ * iterations (stagnation in finite precision); stats.restarts counts both,
+ * and an energy stops as SOFFT_NOT_CONVERGED after 8 restarts.
  *   f       device, [n_y][n_x] (f_per_energy = 0, shared) or [nE][n_y][n_x]
  *   E_host  host, nE energies
  *   x_out   device, [nE][n_y][n_x], written

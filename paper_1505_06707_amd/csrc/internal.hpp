@@ -110,6 +110,10 @@ sofft_status upload_static(Axis& a);
 sofft_status ensure_dt(Axis& a, double dt);
 void free_axis(Axis& a);
 sofft_status dev_upload(DevBuf& b, const void* host, size_t bytes);
+// Raise a kernel's dynamic LDS limit to `limit` bytes, once per kernel (the
+// attribute belongs to the function; the call is made the first time a launch
+// needs more than the default 64 KiB).  Thread-safe.
+sofft_status raise_lds_limit(const void* kernel, size_t limit);
 void dev_free(DevBuf& b);
 
 // Launch shape of a 2D pass: threads per block (0 = default) and grid (0 =

@@ -2,7 +2,9 @@
 // Crank-Nicolson factor, FFT twiddles and kinetic phases (Sec. II), and their
 // device copies.
 #include <cmath>
+#include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -12,6 +14,16 @@ namespace sofft {
 
 static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
+
+sofft_status raise_lds_limit(const void* kernel, size_t limit) {
+  static std::mutex mu;
+  static std::vector<const void*> raised;
+  std::lock_guard<std::mutex> lock(mu);
+  if (std::find(raised.begin(), raised.end(), kernel) != raised.end()) return SOFFT_OK;
+  SOFFT_HIP_TRY(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(limit)));
+  raised.push_back(kernel);
+  return SOFFT_OK;
+}
 
 sofft_status dev_upload(DevBuf& b, const void* host, size_t bytes) {
   if (b.p && b.bytes != bytes) dev_free(b);

@@ -132,11 +132,22 @@ __device__ __forceinline__ cx<double> c_apply(const LineLDS<double>& L, int e, i
   return cmul(cs[p], L[em]) + cmul(cs[m + p], L[e]) + cmul(cs[2 * m + p], L[ep]);
 }
 
+// Threads per block.  Column kernels (K2, K5): at most 1024; lines of 512
+// points take 512 (4 adjacent columns, 64-byte segments), see sse_col_threads.
+// Row kernels (K1, K4, K6): 512.  Smaller blocks let several of them, at
+// different phases, share a CU, so one block's transforms overlap another's
+// loads: measured 8-10% off the 512^2 solves against 1024-thread blocks, at
+// 8 waves per SIMD for the plain kernels (<= 64 VGPRs; K1 needs 72 without
+// the hint, which left one 1024-thread block per CU) and 4 for the banded
+// ones (about 100 VGPRs).
 constexpr int kSseThreads = 1024;
+constexpr int kSseRowThreads = 512;
+constexpr int kSseRowWaves = 8;
+constexpr int kSseBandWaves = 4;
 
 // ---------------------------------------------------------------- K1: row part of A v
 template <int N>
-__global__ void __launch_bounds__(kSseThreads) k_sse_row_mv(SseArgs a, int want, int mode) {
+__global__ void __launch_bounds__(kSseRowThreads, kSseRowWaves) k_sse_row_mv(SseArgs a, int want, int mode) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
   CocgScalars& sc = a.sc[e];
@@ -292,7 +303,7 @@ __device__ __forceinline__ void band_apply(cx<double> (&v)[Shape<N>::P], const L
 
 // ---------------------------------------------------------------- K4: update and forward row FFT
 template <int N, bool BANDED>
-__global__ void __launch_bounds__(kSseThreads) k_sse_row_upd(SseArgs a, int want, int mode) {
+__global__ void __launch_bounds__(kSseRowThreads, BANDED ? kSseBandWaves : kSseRowWaves) k_sse_row_upd(SseArgs a, int want, int mode) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
   CocgScalars& sc = a.sc[e];
@@ -401,7 +412,7 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_col_prec(SseArgs a, int wan
 
 // ---------------------------------------------------------------- K6: inverse row FFT and r^T z
 template <int N, bool BANDED>
-__global__ void __launch_bounds__(kSseThreads) k_sse_row_prec(SseArgs a, int want) {
+__global__ void __launch_bounds__(kSseRowThreads, BANDED ? kSseBandWaves : kSseRowWaves) k_sse_row_prec(SseArgs a, int want) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
   if (a.sc[e].state != want) return;
@@ -518,6 +529,13 @@ __global__ void k_sse_alpha(SseArgs a) {
   sc.first = 0;
 }
 
+// Plain COCG restarts from the true residual after this many iterations
+// without a new minimum of ||r||.  On the 512^2 TFECS workload (2000-6300
+// iterations per energy) single energies otherwise stalled near 1e-6..1e-5;
+// with 2000 the window is reached only by those, whereas 500 and 1000 also
+// restarted (and slowed) healthy energies.
+constexpr int kStallIters = 2000;
+
 // Convergence test on the recurrence residual, then beta and rho.
 __global__ void k_sse_beta(SseArgs a, double rtol, int maxit) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -562,6 +580,17 @@ __global__ void k_sse_beta(SseArgs a, double rtol, int maxit) {
     for (int b = 0; b < a.nblk_row; ++b) rzo = rzo + a.part_rzo[size_t(e) * a.nblk_row + b];
     sc.beta = cdiv(rz - rzo, sc.rho);
     sc.rho = rz;
+    return;
+  }
+  // A recurrence residual that has made no new minimum for kStallIters
+  // iterations has stagnated (in finite precision COCG can plateau on badly
+  // conditioned systems): go to the true-residual check, which restarts the
+  // recurrence from r = f - A x (counted as a restart).
+  if (rr < sc.best_rr) {
+    sc.best_rr = rr;
+    sc.since = 0;
+  } else if (++sc.since >= kStallIters) {
+    sc.state = kCheck;
     return;
   }
   sc.beta = cdiv(rz, sc.rho);
@@ -634,23 +663,17 @@ static int64_t sse_lds_elems(int64_t n) {
 
 template <typename K>
 static sofft_status sse_set_lds(K kernel, size_t bytes) {
-  static bool raised = false;
-  if (bytes > 65536 && !raised) {
-    SOFFT_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(150 * 1024)));
-    raised = true;
-  }
-  return SOFFT_OK;
+  return bytes > 65536 ? raise_lds_limit(reinterpret_cast<const void*>(kernel), 150 * 1024) : SOFFT_OK;
 }
 
 enum SseKernel { kK1, kK2, kK4, kK5, kK6 };
 
 // Lines per block: up to 1024 threads (512 for the radix-3 shapes, which use
 // more registers) and within the LDS budget.
-static int sse_lpb(int64_t n, int lds_line) {
+static int sse_lpb(int64_t n, int lds_line, int threads) {
   const ShapeInfo sh = shape_info(n);
   const int tpl = int(n) / sh.P;
-  const int cap = sh.P == 4 ? kSseThreads : kSseThreads / 2;
+  const int cap = sh.P == 4 ? threads : threads / 2;
   const int unit = tpl >= 64 ? 1 : 64 / tpl;   // whole wavefronts (block sums assume them)
   int lpb = tpl >= cap ? 1 : cap / tpl;
   while (lpb > unit && size_t(lpb) * lds_line * sizeof(cx<double>) > size_t(150 * 1024)) --lpb;
@@ -658,11 +681,18 @@ static int sse_lpb(int64_t n, int lds_line) {
   return lpb > 0 ? lpb : unit;
 }
 
+// Column kernels: lines of 512 points in blocks of 512 threads (the 1024-point
+// lines keep 1024: four columns per block either way); others up to 1024.
+static int sse_col_threads(int64_t n) {
+  const ShapeInfo sh = shape_info(n);
+  return (sh.P == 4 && n / sh.P == 128) ? 512 : kSseThreads;
+}
+
 template <int NX, int NY>
 static sofft_status sse_launch(SseKernel k, const SseArgs& a, int want, int mode, hipStream_t s, Timing& tm) {
   constexpr int TPLX = NX / Shape<NX>::P, TPLY = NY / Shape<NY>::P;
-  const int lpbx = sse_lpb(NX, a.lds_line_x);
-  const int lpby = sse_lpb(NY, a.lds_line_y);
+  const int lpbx = sse_lpb(NX, a.lds_line_x, kSseRowThreads);
+  const int lpby = sse_lpb(NY, a.lds_line_y, sse_col_threads(NY));
   const size_t ldsx = size_t(lpbx) * a.lds_line_x * sizeof(cx<double>);
   const size_t ldsy = size_t(lpby) * a.lds_line_y * sizeof(cx<double>);
   const dim3 grow(a.nblk_row, a.nE), gcol(a.nblk_col, a.nE);
@@ -738,8 +768,9 @@ static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipSt
   const size_t vec = size_t(X.n) * Y.n;
   const int llx = int(std::max<int64_t>(sse_lds_elems(X.n), 64));
   const int lly = int(std::max<int64_t>(sse_lds_elems(Y.n), 64));
-  const int nbr = int((Y.n + sse_lpb(X.n, llx) - 1) / sse_lpb(X.n, llx));
-  const int nbc = int((X.n + sse_lpb(Y.n, lly) - 1) / sse_lpb(Y.n, lly));
+  const int lpr = sse_lpb(X.n, llx, kSseRowThreads), lpc = sse_lpb(Y.n, lly, sse_col_threads(Y.n));
+  const int nbr = int((Y.n + lpr - 1) / lpr);
+  const int nbc = int((X.n + lpc - 1) / lpc);
   const size_t bytes_vec = vec * sizeof(cx<double>);
   const size_t need = 5 * bytes_vec * nE + bytes_vec + size_t(nE) * nbr * (sizeof(double) + 2 * sizeof(cx<double>)) +
                       size_t(nE) * nbc * sizeof(cx<double>) + size_t(nE) * sizeof(CocgScalars) +

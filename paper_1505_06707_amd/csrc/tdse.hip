@@ -719,13 +719,7 @@ constexpr size_t kLdsBudget = 150 * 1024;
 // it needs more than the default 64 KiB.
 template <typename K>
 static sofft_status set_lds(K kernel, size_t bytes) {
-  static bool raised = false;   // one flag per kernel instantiation
-  if (bytes > 65536 && !raised) {
-    SOFFT_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(kLdsBudget)));
-    raised = true;
-  }
-  return SOFFT_OK;
+  return bytes > 65536 ? raise_lds_limit(reinterpret_cast<const void*>(kernel), kLdsBudget) : SOFFT_OK;
 }
 
 #define SOFFT_LENGTH_SWITCH(n, FN, T, ...)        \

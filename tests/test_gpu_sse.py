@@ -80,6 +80,47 @@ def test_iteration_limit_is_reported():
     plan.close()
 
 
+def test_restart_cap_with_unreachable_tolerance():
+    """An unreachable rtol: past the rounding floor of the true residual the
+    recurrence residual keeps falling, so each pass of the recurrence test is
+    followed by a true-residual restart; after 8 restarts the energy is
+    reported as not converged, with the true residual it reached."""
+    plan, oop, ax, ay = _setup(32, 32)
+    f = wl.smooth_source(32, 32, seed=5)
+    x, stats, code = plan.sse_solve(torch.from_numpy(f).cuda(), [0.6], rtol=1e-17, maxit=40000)
+    assert code == 1 and stats[0]["status"] == 1
+    assert stats[0]["restarts"] == 8
+    assert stats[0]["iterations"] < 40000
+    oop.E = complex(0.6)
+    r = f - oop.matvec(x.cpu().numpy()[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) < 1e-12
+    assert abs(stats[0]["rel_residual"] - np.linalg.norm(r) / np.linalg.norm(f)) < 1e-13
+    plan.close()
+
+
+def test_tfecs_full_size_plain_solve_converges_every_energy():
+    """512^2 on the TFECS contour with the paper's FFT preconditioner: 32
+    energies in [0.05, 2.0] to 1e-8, 2000-6300 iterations each.  Single
+    energies used to stagnate near 1e-6..1e-5 (which one depended on the
+    summation order of the dot products); the restart after 2000 iterations
+    without a new residual minimum brings every energy to rtol.  The oracle
+    recomputes f - A x for sampled energies."""
+    c = wl.SSE_2D
+    print("sse TFECS 512^2 x 32 energies, plain preconditioner", flush=True)
+    plan, oop, ax, ay = _setup(c.n, c.n, h=c.h, frac=c.R0_frac, theta=0.5, a2=c.a2, kind="tfecs")
+    f = -wl.smooth_source(c.n, c.n, seed=0)
+    Es = np.linspace(c.E_lo, c.E_hi, 32)
+    x, stats, code = plan.sse_solve(torch.from_numpy(f).cuda(), Es, rtol=c.rtol, maxit=50000)
+    assert code == 0, [(j, s) for j, s in enumerate(stats) if s["status"]][:3]
+    assert max(s["rel_residual"] for s in stats) <= c.rtol
+    xs = x.cpu().numpy()
+    for j in (0, 18, 31):
+        oop.E = complex(Es[j])
+        r = f - oop.matvec(xs[j])
+        assert np.linalg.norm(r) / np.linalg.norm(f) <= c.rtol * (1 + 1e-3), j
+    plan.close()
+
+
 def test_full_workload_true_residual():
     """512^2, h = 0.2, SECS from 80%: the batched 128-energy solve to 1e-8;
     the oracle recomputes f - A x of the GPU solution for sampled energies."""
