@@ -144,10 +144,21 @@ constexpr int kSseThreads = 1024;
 constexpr int kSseRowThreads = 512;
 constexpr int kSseRowWaves = 8;
 constexpr int kSseBandWaves = 4;
+// Launch bound of the column kernels: radix-3 shapes (P = 12) are launched
+// with at most half the threads (sse_lpb), which leaves them the registers
+// they need (with the 1024 bound they spilled 130-175 VGPRs).
+template <int N>
+constexpr int sse_col_bound() { return Shape<N>::P == 4 ? kSseThreads : kSseThreads / 2; }
+// Row kernels likewise; the wave hints apply to radix-4 shapes only (the
+// radix-3 ones hold 12 points per thread and spilled under them).
+template <int N>
+constexpr int sse_row_bound() { return Shape<N>::P == 4 ? kSseRowThreads : kSseRowThreads / 2; }
+template <int N, bool BANDED>
+constexpr int sse_row_waves() { return Shape<N>::P == 4 ? (BANDED ? kSseBandWaves : kSseRowWaves) : 1; }
 
 // ---------------------------------------------------------------- K1: row part of A v
 template <int N>
-__global__ void __launch_bounds__(kSseRowThreads, kSseRowWaves) k_sse_row_mv(SseArgs a, int want, int mode) {
+__global__ void __launch_bounds__(sse_row_bound<N>(), (sse_row_waves<N, false>())) k_sse_row_mv(SseArgs a, int want, int mode) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
   CocgScalars& sc = a.sc[e];
@@ -209,8 +220,10 @@ __device__ __forceinline__ int xcd_block_sse(int b, int nblk) {
 }
 
 // ---------------------------------------------------------------- K2: column part of A v
+// (Holding p in registers for p^T w needs 90 VGPRs.  Reading p again after the
+// transforms with 6 waves per SIMD, 80 VGPRs, measured 4% slower overall.)
 template <int N>
-__global__ void __launch_bounds__(kSseThreads) k_sse_col_mv(SseArgs a, int want, int mode) {
+__global__ void __launch_bounds__(sse_col_bound<N>()) k_sse_col_mv(SseArgs a, int want, int mode) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
   CocgScalars& sc = a.sc[e];
@@ -303,7 +316,7 @@ __device__ __forceinline__ void band_apply(cx<double> (&v)[Shape<N>::P], const L
 
 // ---------------------------------------------------------------- K4: update and forward row FFT
 template <int N, bool BANDED>
-__global__ void __launch_bounds__(kSseRowThreads, BANDED ? kSseBandWaves : kSseRowWaves) k_sse_row_upd(SseArgs a, int want, int mode) {
+__global__ void __launch_bounds__(sse_row_bound<N>(), (sse_row_waves<N, BANDED>())) k_sse_row_upd(SseArgs a, int want, int mode) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
   CocgScalars& sc = a.sc[e];
@@ -354,7 +367,7 @@ __global__ void __launch_bounds__(kSseRowThreads, BANDED ? kSseBandWaves : kSseR
 
 // ---------------------------------------------------------------- K5: column part of P^-1
 template <int N, bool BANDED>
-__global__ void __launch_bounds__(kSseThreads) k_sse_col_prec(SseArgs a, int want) {
+__global__ void __launch_bounds__(sse_col_bound<N>()) k_sse_col_prec(SseArgs a, int want) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
   if (a.sc[e].state != want) return;
@@ -412,7 +425,7 @@ __global__ void __launch_bounds__(kSseThreads) k_sse_col_prec(SseArgs a, int wan
 
 // ---------------------------------------------------------------- K6: inverse row FFT and r^T z
 template <int N, bool BANDED>
-__global__ void __launch_bounds__(kSseRowThreads, BANDED ? kSseBandWaves : kSseRowWaves) k_sse_row_prec(SseArgs a, int want) {
+__global__ void __launch_bounds__(sse_row_bound<N>(), (sse_row_waves<N, BANDED>())) k_sse_row_prec(SseArgs a, int want) {
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int e = blockIdx.y;
   if (a.sc[e].state != want) return;
