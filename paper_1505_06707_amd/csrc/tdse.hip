@@ -297,6 +297,25 @@ __device__ __forceinline__ void cn_block(int lpb, const PassArgs<T>& a, LineOf l
   __syncthreads();
 }
 
+// One element of a state through a global-address-space pointer: the state
+// pointer comes from a select (one state, or the batch's pointer table), so
+// the compiler cannot prove it global and would emit flat accesses, which
+// also count against the LDS counter that the pass's barriers wait on.
+template <typename T>
+__device__ __forceinline__ cx<T> gload(const cx<T>* p) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V v = *(const __attribute__((address_space(1))) V*)(p);
+  return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void gstore(cx<T>* p, cx<T> c) {
+  using V = T __attribute__((ext_vector_type(2)));
+  V v;
+  v.x = c.re;
+  v.y = c.im;
+  *(__attribute__((address_space(1))) V*)(p) = v;
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T>* run_state(const PassArgs<T>& a, int run) {
   return a.runs ? a.runs[run] : a.psi;
@@ -467,6 +486,15 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
 // Column blocks are assigned so that the blocks one XCD runs hold adjacent
 // columns (workgroups go round-robin over the 8 XCDs): neighbouring columns
 // share 128-byte lines, which then meet in the same L2.
+// Slots (s of element t + TPL s) of a column that can hold y-strip nodes: the
+// strip is symmetric and holds at most half of the nodes, so at most N/4 per
+// side, i.e. one slot per side for P = 4 and three for P = 12.
+template <int N>
+__host__ __device__ constexpr int col_edge_slots() { return Shape<N>::P == 4 ? 1 : 3; }
+// k-th edge slot, k < 2 SE: 0 .. SE-1, then P-SE .. P-1.
+template <int P, int SE>
+__device__ __forceinline__ constexpr int edge_slot(int k) { return k < SE ? k : P - 2 * SE + k; }
+
 __device__ __forceinline__ int xcd_block(int b, int nblk) {
   if (nblk % 8 != 0) return b;
   return (b % 8) * (nblk / 8) + b / 8;
@@ -491,45 +519,89 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
     const int gg = live ? g : 0;
     const int run = gg / a.nx, ccol = gg - run * a.nx;
     cx<T>* base = run_state(a, run) + ccol;
+    // The y-strip lies in the first and last SE slots of a column (the host
+    // checks it): those are loaded first, so the CN can start while the
+    // interior slots are still in flight.
+    constexpr int SE = col_edge_slots<N>();
+    // The field, x of this column and the potential-table entries of the
+    // strip are loaded before the state, and used after the state's loads are
+    // issued, so that waiting for them does not wait for the state.
+    double f = 0.0, xc = 0.0;
+    cx<double> vps[2 * SE];
+    double wv[2 * SE];
+    if (cn) {
+      const double* fm = run_field(a, run);
+      f = fm ? fm[step] : 0.0;
+      xc = a.x[ccol];
+#pragma unroll
+      for (int k = 0; k < 2 * SE; ++k) {
+        const int e = t + TPL * edge_slot<P, SE>(k);
+        const bool on = strip_pos<N>(e, a.j0) < a.m;
+        if constexpr (UP) {
+          vps[k] = (on && a.vph) ? a.vph[a.vfull ? size_t(e) * ld + ccol
+                                                 : size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)]
+                                 : cx<double>{1.0, 0.0};
+          wv[k] = (on && a.w) ? a.w[size_t(e) * ld + ccol] : 0.0;
+        } else {
+          vps[k] = (on && a.vph) ? a.vph[size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)]
+                                 : cx<double>{1.0, 0.0};
+        }
+      }
+    }
+    // Loads in storage precision; the interior slots are widened after the CN
+    // (for complex64 a conversion right after its load would wait for it).
+    cx<T> raw[P];
+#pragma unroll
+    for (int k = 0; k < 2 * SE; ++k) {
+      const int s = edge_slot<P, SE>(k);
+      raw[s] = gload(base + size_t(t + TPL * s) * ld);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep the edge loads ahead of the interior ones
+#pragma unroll
+    for (int s = SE; s < P - SE; ++s) raw[s] = gload(base + size_t(t + TPL * s) * ld);
+    __builtin_amdgcn_sched_barrier(0);   // and every load issued before the first wait
     cx<double> v[P];
 #pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = live ? widen(base[size_t(t + TPL * s) * ld]) : cx<double>{0.0, 0.0};
+    for (int k = 0; k < 2 * SE; ++k) {
+      const int s = edge_slot<P, SE>(k);
+      v[s] = widen(raw[s]);
+    }
     if (cn) {
       // C_y and the second potential half-step, on the y-strip only.
-      const double* fm = run_field(a, run);
-      const double f = fm ? fm[step] : 0.0;
-      // exp(-i f x dt/2), the same along the column (W = x); with a caller's W
-      // the phase is taken per node below and lph is 1
-      const cx<double> lph = (UP && a.w) ? cx<double>{1.0, 0.0} : expi(f * a.x[ccol] * a.ht, 0.0);
+      // exp(-i U dt/2) = exp(-i V0 dt/2) exp(-i f W dt/2); with W = x the
+      // field factor is the same along the column
+      const cx<double> lph = expi(f * xc * a.ht, 0.0);
+#pragma unroll
+      for (int k = 0; k < 2 * SE; ++k) {
+        if constexpr (UP) {
+          vps[k] = cmul(vps[k], a.w ? expi(f * wv[k] * a.ht, 0.0) : lph);
+        } else {
+          vps[k] = cmul(vps[k], lph);
+        }
+      }
       const int m = a.m;
       // The strips go to a contiguous area per column (odd stride 2m + 1), not
       // the interleaved FFT layout: one wavefront's positions are then
       // consecutive in LDS and the reduction is free of bank conflicts.
       const int cstride = 2 * m + 1;
       const LineLDS<X> Lc{lines, c * cstride, 1};
-      cx<double> vps[P];
 #pragma unroll
-      for (int s = 0; s < P; ++s) {
-        const int e = t + TPL * s;
-        const int p = strip_pos<N>(e, a.j0);
-        if constexpr (UP) {
-          vps[s] = (p < m && a.vph) ? a.vph[a.vfull ? size_t(e) * ld + ccol
-                                                    : size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)]
-                                    : cx<double>{1.0, 0.0};
-          if (p < m && a.w) vps[s] = cmul(vps[s], expi(f * a.w[size_t(e) * ld + ccol] * a.ht, 0.0));
-        } else {
-          vps[s] = (p < m && a.vph) ? a.vph[size_t(vfold(e, N)) * (a.nx / 2) + vfold(ccol, a.nx)] : cx<double>{1.0, 0.0};
-        }
+      for (int k = 0; k < 2 * SE; ++k) {
+        const int s = edge_slot<P, SE>(k);
+        const int p = strip_pos<N>(t + TPL * s, a.j0);
         if (p < m) Lc[p] = narrow<X>(v[s]);
       }
       cn_block<T, N>(lpb, a, [&](int ln) { return LineLDS<X>{lines, ln * cstride, 1}; });
 #pragma unroll
-      for (int s = 0; s < P; ++s) {
+      for (int k = 0; k < 2 * SE; ++k) {
+        const int s = edge_slot<P, SE>(k);
         const int p = strip_pos<N>(t + TPL * s, a.j0);
-        if (p < m) v[s] = cmul(2.0 * widen(Lc[cn_result(m, a.levels) + p]) - v[s], cmul(vps[s], lph));
+        if (p < m) v[s] = cmul(2.0 * widen(Lc[cn_result(m, a.levels) + p]) - v[s], vps[k]);
       }
       __syncthreads();
     }
+#pragma unroll
+    for (int s = SE; s < P - SE; ++s) v[s] = widen(raw[s]);
     cx<double> kin[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
@@ -547,7 +619,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
     }
     if (live) {
 #pragma unroll
-      for (int s = 0; s < P; ++s) base[size_t(t + TPL * s) * ld] = narrow<T>(v[s]);
+      for (int s = 0; s < P; ++s) gstore(base + size_t(t + TPL * s) * ld, narrow<T>(v[s]));
     }
   };
   run_tiles<PERSIST>(a.ntiles, body);
@@ -787,6 +859,17 @@ static sofft_status pass(PassArgs<T> a, PassLaunch cfg, hipStream_t s, Timing* t
   }
   sofft_status st = pass_set_lds<T, N, ROW>(lds);
   if (st != SOFFT_OK) return st;
+  if (!ROW && a.do_pot && a.m > 0) {
+    // the column pass applies the CN to the edge slots only
+    constexpr int SE = col_edge_slots<N>(), P = Shape<N>::P;
+    for (int q = 0; q < a.m; ++q) {
+      const int sl = ((a.j0 + q) % N) / TPL;
+      if (sl >= SE && sl < P - SE) {
+        set_error("ECS strip of the y axis reaches beyond the outer quarters of the axis");
+        return SOFFT_EUNSUPPORTED;
+      }
+    }
+  }
   const int lines = a.nruns * (ROW ? a.ny : a.nx);
   a.ntiles = (lines + lpb - 1) / lpb;
   // a caller's potential (single plans only) takes the one-block-per-tile grid
