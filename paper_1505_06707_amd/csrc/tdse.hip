@@ -371,9 +371,10 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     const int gg = live ? g : 0;
     const int run = gg / a.ny, crow = gg - run * a.ny;
     cx<T>* line = run_state(a, run) + size_t(crow) * N;
+    // branch-free global loads (dead lanes read row 0 of run 0 and store nothing)
     cx<double> v[P];
 #pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = live ? widen(line[t + TPL * s]) : cx<double>{0.0, 0.0};
+    for (int s = 0; s < P; ++s) v[s] = widen(gload(line + t + TPL * s));
     // kinetic factors, static potential phases and x of the field term: with
     // P = 4 fetched before the transforms (latency hidden behind them); the
     // P = 12 shapes fetch them where they are used, which keeps 120 VGPRs
@@ -477,7 +478,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     }
     if (live) {
 #pragma unroll
-      for (int s = 0; s < P; ++s) line[t + TPL * s] = narrow<T>(v[s]);
+      for (int s = 0; s < P; ++s) gstore(line + t + TPL * s, narrow<T>(v[s]));
     }
   };
   run_tiles<PERSIST>(a.ntiles, body);
