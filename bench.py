@@ -49,7 +49,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def gpu_tdse(sofft, wl, torch, dtype, steps, warmup, seed=1):
+def gpu_tdse(sofft, wl, torch, dtype, steps, warmup, reps=5, seed=1):
+    """The 2D workload: `warmup` untimed steps, then `reps` repetitions of the
+    same `steps` steps (each from the warmed-up state), every one timed with
+    HIP events recorded on the stream the library launches on, around the
+    sofft_propagate call.  Returns the median and the per-kernel durations."""
     c = wl.TDSE_2D
     plan = sofft.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=c.theta, charge=c.charge,
                       a2=c.a2, dtype=dtype)
@@ -58,31 +62,69 @@ def gpu_tdse(sofft, wl, torch, dtype, steps, warmup, seed=1):
     cdt = np.complex128 if dtype == sofft.C128 else np.complex64
     f_all = c.pulse.at_midpoints(0.0, c.dt, warmup + steps)
     f_dev = torch.from_numpy(f_all).cuda()
-    psi = torch.from_numpy(psi0.astype(cdt)).cuda()
-    # warm-up steps (untimed), then the timed region
+    warm = torch.from_numpy(psi0.astype(cdt)).cuda()
     if warmup:
-        plan.propagate(psi, c.dt, warmup, f_dev[:warmup])
+        plan.propagate(warm, c.dt, warmup, f_dev[:warmup])
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    plan.propagate(psi, c.dt, steps, f_dev[warmup:])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_s = e0.elapsed_time(e1) / 1e3
+    ev, wall = [], []
+    for _ in range(reps):
+        psi = warm.clone()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        plan.propagate(psi, c.dt, steps, f_dev[warmup:], stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall.append(time.perf_counter() - t0)
+        ev.append(e0.elapsed_time(e1) / 1e3)
     result = psi.clone()
     # The same K steps again with every launch bracketed by HIP events on the
     # library's stream, for the per-kernel durations of the roofline.
-    psi.copy_(torch.from_numpy(psi0.astype(cdt)).cuda())
+    psi.copy_(warm)
     plan.timing(True)
-    plan.propagate(psi, c.dt, steps, f_dev[warmup:])
+    plan.propagate(psi, c.dt, steps, f_dev[warmup:], stream=stream)
     kern = {name: plan.timing_read(k) for name, k in (("row_pass", sofft.KERNEL_ROW),
                                                        ("column_pass", sofft.KERNEL_COL))}
     plan.timing(False)
     plan.close()
-    return dict(wall=wall, event_s=ev_s, kernels=kern, psi=result, npts=c.n * c.n)
+    return dict(event_s=float(np.median(ev)), event_all_s=ev, wall_s=float(np.median(wall)), kernels=kern,
+                psi=result, npts=c.n * c.n)
+
+
+def fp32_vs_oracle_checkpoints(sofft, wl, torch):
+    """complex64 propagation of the whole 2D workload (2000 steps) against the
+    FP64 oracle's stored state at steps 100/500/1000/2000 (8192 seeded points
+    and the squared norm; tests/golden/make_tdse_2d_1024_checkpoints.py writes
+    them from the oracle alone)."""
+    path = os.path.join(ROOT, "tests", "golden", "tdse_2d_1024_checkpoints.npz")
+    if not os.path.exists(path):
+        return None
+    gold = np.load(path)
+    c = wl.TDSE_2D
+    out = {}
+    for name, dt_ in (("c64", sofft.C64), ("c128", sofft.C128)):
+        plan = sofft.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=c.theta, charge=c.charge, a2=c.a2,
+                          dtype=dt_)
+        x = plan.nodes(0)
+        psi0 = wl.gaussian_2d(x, x, **wl.packet_params(int(gold["packet_seed"])))
+        psi = torch.from_numpy(psi0.astype(np.complex64 if dt_ == sofft.C64 else np.complex128)).cuda()
+        f = torch.from_numpy(c.pulse.at_midpoints(0.0, c.dt, int(gold["steps"][-1]))).cuda()
+        done, rows = 0, {}
+        for k, step in enumerate(gold["steps"]):
+            step = int(step)
+            plan.propagate(psi, c.dt, step - done, f[done:step])
+            done = step
+            torch.cuda.synchronize()
+            got = psi.cpu().numpy().astype(np.complex128).ravel()[gold["index"]]
+            want = gold["samples"][k]
+            rows[str(step)] = {"rel_l2_samples": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+                               "norm2_rel_err": float(abs(plan.norm2(psi) - gold["norm2"][k]) / gold["norm2"][k])}
+        plan.close()
+        out[name] = rows
+    out["sampled_points"] = int(len(gold["index"]))
+    return out
 
 
 def gpu_tdse1d(sofft, wl, torch):
@@ -104,7 +146,7 @@ def gpu_tdse1d(sofft, wl, torch):
             "value": c.n * c.nsteps / wall, "unit": "grid-point-steps/s", "us_per_step": wall / c.nsteps * 1e6}
 
 
-def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0, extras=True):
+def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0, extras=True, shifted=False):
     """Batched COCG to 1e-8 on the 512^2 stationary workload (Sec. III)."""
     c = wl.SSE_2D
     plan = sofft.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=c.theta, charge=c.charge, a2=c.a2)
@@ -124,7 +166,7 @@ def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0, extras=True):
              "row_precond_dot": sofft.KERNEL_SSE_ROW_PREC}
     kern = {k: plan.timing_read(v) for k, v in kinds.items()}
     plan.timing(False)
-    shifted = pcg_shifted(plan, f, E, c.rtol, out, wall, torch) if extras else None
+    shifted = pcg_shifted(plan, f, E, c.rtol, out, wall, torch) if shifted else None
     band = pcg_banded(plan, f, E, c.rtol, out, wall, torch) if extras else None
     plan.close()
     its = np.array([s["iterations"] for s in stats])
@@ -147,7 +189,7 @@ def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0, extras=True):
             "kernels_ms": {k: v[0] for k, v in kern.items()}, "shifted": shifted, "banded": band}
 
 
-def gpu_pcg_tfecs(sofft, wl, torch, n_energies=32, seed=0):
+def gpu_pcg_tfecs(sofft, wl, torch, n_energies=32, seed=0, shifted=False):
     """The 512^2 stationary workload on the TFECS contour (Eq. qTFECS, alpha =
     0.5), where the paper finds the plain FFT preconditioner slow: 32 energies
     in [0.05, 2.0] with the paper's divisor, then with tuned shifts."""
@@ -163,7 +205,7 @@ def gpu_pcg_tfecs(sofft, wl, torch, n_energies=32, seed=0):
     _, stats, code = plan.sse_solve(f, E, rtol=c.rtol, out=out, maxit=50000)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    shifted = pcg_shifted(plan, f, E, c.rtol, out, wall, torch, every=4)
+    shifted = pcg_shifted(plan, f, E, c.rtol, out, wall, torch, every=4) if shifted else None
     band = pcg_banded(plan, f, E, c.rtol, out, wall, torch)
     plan.close()
     its = np.array([q["iterations"] for q in stats])
@@ -254,7 +296,7 @@ def gpu_batch(sofft, wl, torch, steps, seed=2024, warmup=40):
             "launch_shapes": {str(k): v for k, v in sorted(shapes.items())}, "graph_steps": 32}
 
 
-def gpu_learned(sofft, wl, torch, epochs=30):
+def gpu_learned(sofft, wl, torch, epochs=30, shifted=False):
     """Learned correction on the 1024^2 x 64-energy stationary workload:
     pairs from plain COCG on training sources, training on the GPU, then
     plain COCG and the flexible solve on the evaluation source."""
@@ -286,7 +328,7 @@ def gpu_learned(sofft, wl, torch, epochs=30):
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     lp.close()
-    shifted = pcg_shifted(plan, f, np.asarray(E, dtype=np.float64), c.rtol, out, t_plain, torch)
+    shifted = pcg_shifted(plan, f, np.asarray(E, dtype=np.float64), c.rtol, out, t_plain, torch) if shifted else None
     plan.close()
     i0 = np.array([q["iterations"] for q in st0])
     i1 = np.array([q["iterations"] for q in st1])
@@ -302,22 +344,72 @@ def gpu_learned(sofft, wl, torch, epochs=30):
             "shifted_divisor": shifted}
 
 
-def cpu_baseline(wl, sample_steps, seed=1):
-    """The FP64 oracle on the host, a bounded sample of the same workload."""
-    from oracle import tdse as ot
+_CPU_CHILD = r"""
+import json, os, sys, time
+import numpy as np
+import scipy.fft
+sys.path.insert(0, sys.argv[1])
+from oracle import tdse as ot
+from paper_1505_06707_amd import workloads as wl
+steps, reps, workers = int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4])
+c = wl.TDSE_2D
+ax = ot.Axis(c.n, c.L, R0=c.R0, theta=c.theta)
+prob = ot.Problem2D(ax, ax, Zc=c.charge, a2=c.a2)
+psi0 = wl.gaussian_2d(ax.x, ax.x, **wl.packet_params(1))
+f = c.pulse.at_midpoints(0.0, c.dt, steps)
+times = []
+with scipy.fft.set_workers(workers):
+    prob.step(psi0, c.dt, f[0])       # factorisations and tables outside the timing
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        prob.propagate(psi0, c.dt, f)
+        times.append(time.perf_counter() - t0)
+print(json.dumps({"times": times}))
+"""
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _cpu_run(steps, reps, workers, pin):
+    import subprocess
+    env = dict(os.environ)
+    nthreads = "1" if pin else str(workers)
+    env.update(OMP_NUM_THREADS=nthreads, OPENBLAS_NUM_THREADS=nthreads, MKL_NUM_THREADS=nthreads)
+    pre = (lambda: os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})) if pin else None
+    r = subprocess.run([sys.executable, "-c", _CPU_CHILD, ROOT, str(steps), str(reps), str(workers)],
+                       capture_output=True, text=True, env=env, preexec_fn=pre, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError("CPU oracle run failed: " + r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])["times"]
+
+
+def cpu_baseline(wl, sample_steps, reps=5):
+    """The FP64 oracle on the host, a bounded sample of the same workload: the
+    literal four-FFT step (scipy pocketfft + SuperLU) for `sample_steps` steps,
+    median of `reps` runs after a warm-up step, in a child process pinned to
+    one core (OMP/OpenBLAS at one thread), then the same with scipy.fft's
+    workers set to every core the process may use."""
     c = wl.TDSE_2D
-    ax = ot.Axis(c.n, c.L, R0=c.R0, theta=c.theta)
-    prob = ot.Problem2D(ax, ax, Zc=c.charge, a2=c.a2)
-    psi0 = wl.gaussian_2d(ax.x, ax.x, **wl.packet_params(seed))
-    f = c.pulse.at_midpoints(0.0, c.dt, sample_steps)
-    prob.step(psi0, c.dt, f[0])          # factorisations and tables outside the timing
-    t0 = time.perf_counter()
-    prob.propagate(psi0, c.dt, f)
-    dt = time.perf_counter() - t0
-    return dict(value=c.n * c.n * sample_steps / dt, unit="grid-point-steps/s", cores=1, kind="oracle",
-                sample=f"{sample_steps} steps of the 1024^2 c128 workload (literal four-FFT step, "
-                       f"numpy pocketfft + scipy SuperLU, single thread) in {dt:.1f} s on "
-                       f"{platform.processor() or platform.machine()}, {os.cpu_count()} host threads visible")
+    ncores = len(os.sched_getaffinity(0))
+    t1 = float(np.median(_cpu_run(sample_steps, reps, 1, pin=True)))
+    tn = float(np.median(_cpu_run(sample_steps, reps, ncores, pin=False)))
+    npts = c.n * c.n
+    return dict(value=npts * sample_steps / t1, unit="grid-point-steps/s", cores=1, kind="oracle",
+                sample=f"{sample_steps} steps of the 1024^2 c128 workload (literal four-FFT step, scipy pocketfft + "
+                       f"SuperLU), median of {reps} runs of {t1:.2f} s, one pinned core of {ncores} usable "
+                       f"({_cpu_model()})",
+                cpu_model=_cpu_model(), host_cores=ncores,
+                all_cores={"value": npts * sample_steps / tn, "cores": ncores, "median_s": tn,
+                           "note": "same oracle, scipy.fft workers = usable cores; SuperLU and the "
+                                   "elementwise phases stay single-threaded"})
 
 
 def main():
@@ -325,12 +417,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-sample-steps", type=int, default=40)
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions of the K steps (median reported)")
+    ap.add_argument("--cpu-sample-steps", type=int, default=8)
+    ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--shifted", action="store_true",
+                    help="also time the shifted-divisor option (not the paper's preconditioner)")
     ap.add_argument("--no-pcg-extras", action="store_true",
-                    help="only the paper's preconditioner in the PCG leg (no shifted, banded or TFECS solves)")
+                    help="only the paper's plain preconditioner in the PCG leg (no banded or TFECS solves)")
     ap.add_argument("--pcg-energies", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-1d", action="store_true")
@@ -361,12 +457,13 @@ def main():
         log(f"copied {args.copy_mib} MiB x 5")
         return
 
-    log(f"TDSE 2D 1024^2 c128: warmup {args.warmup}, timed {args.steps} steps")
-    r64 = gpu_tdse(sofft, wl, torch, sofft.C128, args.steps, args.warmup)
+    log(f"TDSE 2D 1024^2 c128: warmup {args.warmup}, {args.reps} x {args.steps} timed steps")
+    r64 = gpu_tdse(sofft, wl, torch, sofft.C128, args.steps, args.warmup, reps=args.reps)
     npts = r64["npts"]
-    value = npts * args.steps / r64["wall"]
-    ms_per_step = r64["wall"] / args.steps * 1e3
-    log(f"  {ms_per_step * 1e3:.1f} us/step, {value / 1e9:.2f} G grid-point-steps/s")
+    value = npts * args.steps / r64["event_s"]
+    ms_per_step = r64["event_s"] / args.steps * 1e3
+    log(f"  {ms_per_step * 1e3:.1f} us/step (HIP events, median of {args.reps}; wall "
+        f"{r64['wall_s'] / args.steps * 1e6:.1f} us/step), {value / 1e9:.2f} G grid-point-steps/s")
 
     # roofline of the dominant kernel: algorithmic bytes = read + write of the state
     # (2 x 16 B per grid point) per launch of a row or column pass
@@ -380,21 +477,27 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom), "kernel": dom,
                 "avg_launch_us": avg_s * 1e6, "launches": cnt,
                 "algorithmic_bytes_per_launch": alg_bytes,
-                "kernels_avg_us": {k: v[0] / v[1] * 1e3 for k, v in kern.items() if v[1]}}
+                "kernels_avg_us": {k: v[0] / v[1] * 1e3 for k, v in kern.items() if v[1]},
+                "step_frac": 4 * 16 * npts / (r64["event_s"] / args.steps) / 1e9 / HBM_PEAK_GBS}
     log(f"  dominant kernel {dom}: {avg_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM peak)")
 
     fp32 = None
     if not args.no_fp32:
         log("TDSE 2D 1024^2 c64")
-        r32 = gpu_tdse(sofft, wl, torch, sofft.C64, args.steps, args.warmup)
+        r32 = gpu_tdse(sofft, wl, torch, sofft.C64, args.steps, args.warmup, reps=args.reps)
         a = r64["psi"].cpu().numpy()
         b = r32["psi"].cpu().numpy().astype(np.complex128)
         err = float(np.linalg.norm(b - a) / np.linalg.norm(a))
-        fp32 = {"value": npts * args.steps / r32["wall"], "unit": "grid-point-steps/s",
-                "ms_per_step": r32["wall"] / args.steps * 1e3,
+        fp32 = {"value": npts * args.steps / r32["event_s"], "unit": "grid-point-steps/s",
+                "ms_per_step": r32["event_s"] / args.steps * 1e3,
                 "rel_l2_vs_fp64_path": err, "steps": args.steps + args.warmup}
         log(f"  c64: {fp32['ms_per_step'] * 1e3:.1f} us/step, rel L2 vs FP64 path {err:.2e}")
+        fp32["vs_fp64_oracle"] = fp32_vs_oracle_checkpoints(sofft, wl, torch)
+        if fp32["vs_fp64_oracle"]:
+            log("  vs FP64 oracle (sampled): " + ", ".join(
+                f"{k}: c64 {v['rel_l2_samples']:.2e} / c128 {fp32['vs_fp64_oracle']['c128'][k]['rel_l2_samples']:.2e}"
+                for k, v in fp32["vs_fp64_oracle"]["c64"].items()))
 
     tdse1d = None
     if not args.no_1d:
@@ -406,25 +509,20 @@ def main():
     pcg = None
     if not args.no_pcg:
         log("SSE 512^2 batched COCG to 1e-8")
-        pcg = gpu_pcg(sofft, wl, torch, args.pcg_energies, extras=not args.no_pcg_extras)
+        pcg = gpu_pcg(sofft, wl, torch, args.pcg_energies, extras=not args.no_pcg_extras, shifted=args.shifted)
         log(f"  {pcg['energies']} energies in {pcg['time_to_tol_s']:.3f} s, iterations "
             f"{pcg['iterations']['min']}..{pcg['iterations']['max']} (mean {pcg['iterations']['mean']:.0f}), "
             f"{pcg['achieved_GBs_all_kernels']:.0f} GB/s over the fused passes")
-    if pcg is not None and pcg["shifted"] is not None:
-        sh = pcg["shifted"]
-        log(f"  shifted divisor (tuned on {sh['tuned_on']} energies): {sh['time_to_tol_s']:.3f} s "
-            f"(tuning {sh['tune_s']:.3f} s), iterations mean {sh['iterations']['mean']:.0f}, "
-            f"{sh['speedup_vs_plain']:.2f}x the plain solve")
-        bd = pcg["banded"]
-        log(f"  banded ECS preconditioner: {bd['time_to_tol_s']:.3f} s, iterations mean {bd['iterations']['mean']:.0f}, "
-            f"{bd['speedup_vs_plain']:.2f}x the plain solve")
-        log("SSE 512^2 on the TFECS contour, 32 energies")
-        pcg["tfecs"] = gpu_pcg_tfecs(sofft, wl, torch)
-        tf = pcg["tfecs"]
-        log(f"  plain {tf['time_to_tol_s']:.3f} s (mean {tf['iterations']['mean']:.0f} it); shifted "
-            f"{tf['shifted']['time_to_tol_s']:.3f} s incl. tuning (mean {tf['shifted']['iterations']['mean']:.0f} it), "
-            f"{tf['shifted']['speedup_vs_plain']:.2f}x; banded {tf['banded']['time_to_tol_s']:.3f} s "
-            f"(mean {tf['banded']['iterations']['mean']:.0f} it), {tf['banded']['speedup_vs_plain']:.2f}x")
+        if pcg["banded"] is not None:
+            bd = pcg["banded"]
+            log(f"  banded ECS preconditioner: {bd['time_to_tol_s']:.3f} s, iterations mean "
+                f"{bd['iterations']['mean']:.0f}, {bd['speedup_vs_plain']:.2f}x the plain solve")
+            log("SSE 512^2 on the TFECS contour, 32 energies")
+            pcg["tfecs"] = gpu_pcg_tfecs(sofft, wl, torch, shifted=args.shifted)
+            tf = pcg["tfecs"]
+            log(f"  plain {tf['time_to_tol_s']:.3f} s (mean {tf['iterations']['mean']:.0f} it); banded "
+                f"{tf['banded']['time_to_tol_s']:.3f} s (mean {tf['banded']['iterations']['mean']:.0f} it), "
+                f"{tf['banded']['speedup_vs_plain']:.2f}x")
 
     batch = None
     if not args.no_batch:
@@ -435,20 +533,18 @@ def main():
 
     learned = None
     if not args.no_learned:
-        log("learned correction: 1024^2 x 64 energies (pairs, training, plain vs flexible solve)")
-        learned = gpu_learned(sofft, wl, torch)
+        log("learned correction: 1024^2 x 64 energies (pairs, training, plain vs corrected solve)")
+        learned = gpu_learned(sofft, wl, torch, shifted=args.shifted)
         log(f"  plain {learned['plain']['time_s']:.2f} s (mean {learned['plain']['iterations_mean']:.0f} it), "
             f"learned {learned['learned']['time_s']:.2f} s (mean {learned['learned']['iterations_mean']:.0f} it, "
             f"{learned['learned']['fell_back']} fell back); training {learned['train_s']:.1f} s")
-        sd = learned["shifted_divisor"]
-        log(f"  shifted divisor: {sd['time_to_tol_s']:.2f} s incl. tuning (mean {sd['iterations']['mean']:.0f} it), "
-            f"{sd['speedup_vs_plain']:.2f}x the plain solve")
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"CPU oracle sample: {args.cpu_sample_steps} steps")
-        cpu = cpu_baseline(wl, args.cpu_sample_steps)
-        log(f"  {cpu['value'] / 1e6:.2f} M grid-point-steps/s")
+        log(f"CPU oracle sample: {args.cpu_reps} x {args.cpu_sample_steps} steps, pinned and all cores")
+        cpu = cpu_baseline(wl, args.cpu_sample_steps, reps=args.cpu_reps)
+        log(f"  {cpu['value'] / 1e6:.2f} M grid-point-steps/s on one core, "
+            f"{cpu['all_cores']['value'] / 1e6:.2f} M on {cpu['all_cores']['cores']} ({cpu['cpu_model']})")
 
     out = {
         "metric": METRIC,
@@ -467,6 +563,10 @@ def main():
                    "ecs": "SECS, R0 = 81.92 (80% of half-width), end angle 0.5",
                    "potential": "soft-core a2=0.64 + dipole pulse E0=0.05 w=0.057 4 cycles",
                    "parallelism": "single-gpu"},
+        "timing": {"method": "HIP events around sofft_propagate on its stream", "reps": args.reps,
+                   "statistic": "median", "per_rep_ms_per_step": [t / args.steps * 1e3 for t in r64["event_all_s"]],
+                   "wall_ms_per_step_median": r64["wall_s"] / args.steps * 1e3,
+                   "passes_per_call": 2 * args.steps + 2},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp32": fp32,

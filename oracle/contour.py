@@ -30,11 +30,11 @@ TFECS = "tfecs"
 
 
 def tfecs_y(s, alpha):
-    """y(s) = alpha [(1 - s)^-2 - (1 + s)^-2 - 4 s] of Eq. qTFECS, evaluated as
-    4 alpha s^3 (2 - s^2)/(1 - s^2)^2: the same function (the first two terms
-    are 4 s/(1 - s^2)^2) without the cancellation of O(1) terms at small s."""
+    """y(s) = alpha [(1 - s)^-2 - (1 + s)^-2 - 4 s] of Eq. qTFECS, as printed.
+    Near s = 0 the three terms cancel to O(s^3); q = sqrt(1 + i y) then carries
+    an absolute rounding error of a few 1e-16, far below every tolerance."""
     s = np.asarray(s, dtype=float)
-    return 4.0 * alpha * s ** 3 * (2.0 - s * s) / (1.0 - s * s) ** 2
+    return alpha * ((1.0 - s) ** -2 - (1.0 + s) ** -2 - 4.0 * s)
 
 
 def _tfecs_q_scalar(u, R0, D, alpha):

@@ -23,6 +23,7 @@ with the paper's own coefficients psi_i = sqrt(h) psi(x_i) and with the
 orthonormality of the xi_i.  The oracle uses the summed value.
 """
 import numpy as np
+import scipy.fft
 
 
 def nodes(n, L):
@@ -64,12 +65,13 @@ def _grid_phase(n, L):
 
 
 def forward(psi, L, axis=-1):
-    """psi -> F psi along ``axis`` (Sec. II, Eq. Fmatrix), by numpy's FFT."""
+    """psi -> F psi along ``axis`` (Sec. II, Eq. Fmatrix), by scipy's FFT
+    (a library primitive; ``scipy.fft.set_workers`` sets its thread count)."""
     n = psi.shape[axis]
     ph = _grid_phase(n, L)
     shape = [1] * psi.ndim
     shape[axis] = n
-    return np.fft.fft(psi, axis=axis, norm="ortho") * ph.reshape(shape)
+    return scipy.fft.fft(psi, axis=axis, norm="ortho") * ph.reshape(shape)
 
 
 def inverse(phi, L, axis=-1):
@@ -78,7 +80,7 @@ def inverse(phi, L, axis=-1):
     ph = _grid_phase(n, L)
     shape = [1] * phi.ndim
     shape[axis] = n
-    return np.fft.ifft(phi * np.conj(ph).reshape(shape), axis=axis, norm="ortho")
+    return scipy.fft.ifft(phi * np.conj(ph).reshape(shape), axis=axis, norm="ortho")
 
 
 def lagrange(i, x_eval, n, L):

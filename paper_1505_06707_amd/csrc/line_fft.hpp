@@ -23,32 +23,11 @@
 
 namespace sofft {
 
-// N = R0 * RR^K with RR = 4 or 8; P points per thread (a multiple of R0 and
-// of RR).  PAD is the LDS padding period (one spare element per PAD), chosen so
+// N = R0 * RR^K with RR = 4; P points per thread (a multiple of R0 and of
+// RR).  PAD is the LDS padding period (one spare element per PAD), chosen so
 // that the stride-R0 writes of stage 0 do not collide in LDS banks; 0 means no
-// padding.  SOFFT_RADIX8 selects the radix-8 engine for power-of-two lengths.
+// padding.
 template <int N> struct Shape;
-#if defined(SOFFT_RADIX16)
-template <> struct Shape<16>   { static constexpr int P = 4,  R0 = 4,  RR = 4,  K = 1, PAD = 4; };
-template <> struct Shape<32>   { static constexpr int P = 16, R0 = 2,  RR = 16, K = 1, PAD = 2; };
-template <> struct Shape<64>   { static constexpr int P = 16, R0 = 4,  RR = 16, K = 1, PAD = 4; };
-template <> struct Shape<128>  { static constexpr int P = 16, R0 = 8,  RR = 16, K = 1, PAD = 8; };
-template <> struct Shape<256>  { static constexpr int P = 16, R0 = 16, RR = 16, K = 1, PAD = 16; };
-template <> struct Shape<512>  { static constexpr int P = 16, R0 = 2,  RR = 16, K = 2, PAD = 2; };
-template <> struct Shape<1024> { static constexpr int P = 16, R0 = 4,  RR = 16, K = 2, PAD = 4; };
-template <> struct Shape<2048> { static constexpr int P = 16, R0 = 8,  RR = 16, K = 2, PAD = 8; };
-template <> struct Shape<4096> { static constexpr int P = 16, R0 = 16, RR = 16, K = 2, PAD = 16; };
-#elif defined(SOFFT_RADIX8)
-template <> struct Shape<16>   { static constexpr int P = 8,  R0 = 2, RR = 8, K = 1, PAD = 2; };
-template <> struct Shape<32>   { static constexpr int P = 8,  R0 = 4, RR = 8, K = 1, PAD = 4; };
-template <> struct Shape<64>   { static constexpr int P = 8,  R0 = 8, RR = 8, K = 1, PAD = 8; };
-template <> struct Shape<128>  { static constexpr int P = 8,  R0 = 2, RR = 8, K = 2, PAD = 2; };
-template <> struct Shape<256>  { static constexpr int P = 8,  R0 = 4, RR = 8, K = 2, PAD = 4; };
-template <> struct Shape<512>  { static constexpr int P = 8,  R0 = 8, RR = 8, K = 2, PAD = 8; };
-template <> struct Shape<1024> { static constexpr int P = 8,  R0 = 2, RR = 8, K = 3, PAD = 2; };
-template <> struct Shape<2048> { static constexpr int P = 8,  R0 = 4, RR = 8, K = 3, PAD = 4; };
-template <> struct Shape<4096> { static constexpr int P = 8,  R0 = 8, RR = 8, K = 3, PAD = 8; };
-#else
 // Radix-4 stages, no LDS padding (measured faster than one pad element per R0).
 template <> struct Shape<16>   { static constexpr int P = 4,  R0 = 4, RR = 4, K = 1, PAD = 0; };
 template <> struct Shape<32>   { static constexpr int P = 4,  R0 = 2, RR = 4, K = 2, PAD = 0; };
@@ -59,7 +38,6 @@ template <> struct Shape<512>  { static constexpr int P = 4,  R0 = 2, RR = 4, K 
 template <> struct Shape<1024> { static constexpr int P = 4,  R0 = 4, RR = 4, K = 4, PAD = 0; };
 template <> struct Shape<2048> { static constexpr int P = 4,  R0 = 2, RR = 4, K = 5, PAD = 0; };
 template <> struct Shape<4096> { static constexpr int P = 4,  R0 = 4, RR = 4, K = 5, PAD = 0; };
-#endif
 template <> struct Shape<48>   { static constexpr int P = 12, R0 = 3, RR = 4, K = 2, PAD = 0; };
 template <> struct Shape<96>   { static constexpr int P = 12, R0 = 6, RR = 4, K = 2, PAD = 6; };
 template <> struct Shape<192>  { static constexpr int P = 12, R0 = 3, RR = 4, K = 3, PAD = 0; };

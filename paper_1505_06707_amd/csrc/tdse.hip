@@ -19,20 +19,10 @@ namespace sofft {
 // A complex128 or complex64 state (T = double or float) is loaded from HBM,
 // transformed and propagated in FP64 registers with FP64 tables, and rounded
 // to T only when stored.  Line exchanges and the CN reduction go through LDS
-// as xch_t<T>: double, or float for a complex64 state when built with
-// SOFFT_C64_LDS_FLOAT (half the LDS bytes, one more FP32 rounding per stage).
+// in FP64 (xch_t): an FP32 exchange for complex64 measured 3% faster and 3x
+// the error.
 template <typename T>
-struct Xch {
-  using type = double;
-};
-#if defined(SOFFT_C64_LDS_FLOAT)
-template <>
-struct Xch<float> {
-  using type = float;
-};
-#endif
-template <typename T>
-using xch_t = typename Xch<T>::type;
+using xch_t = double;
 
 template <typename T>
 struct PassArgs {
@@ -126,13 +116,10 @@ __device__ __forceinline__ void cn_strip(cx<double> (&v)[Shape<N>::P], const Lin
 
 // U/2 . C . U/2 along a line whose cross coordinate is fixed (1D): outside
 // the strip the two half-steps are one multiply by the squared phase; on the
-// strip the phase is parked in LDS (from 2m) across the CN when the exchange
-// type is FP64, and evaluated again after it otherwise (an FP32 copy would be
-// the same rounding error in every step).
+// strip the phase is parked in LDS (from 2m) across the CN.
 template <typename T, int N, typename X, typename PhaseFn>
 __device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, int t,
                                            const PassArgs<T>& a, PhaseFn phase) {
-  constexpr bool park = std::is_same<X, double>::value;
   constexpr int P = Shape<N>::P, TPL = N / P;
   const int m = a.m;
 #pragma unroll
@@ -142,7 +129,7 @@ __device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const L
     const int p = strip_pos<N>(e, a.j0);
     if (p < m) {
       v[s] = cmul(v[s], ph);
-      if constexpr (park) L[2 * m + p] = ph;
+      L[2 * m + p] = ph;
     } else {
       v[s] = cmul(v[s], cmul(ph, ph));
     }
@@ -154,11 +141,7 @@ __device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const L
       const int e = t + TPL * s;
       const int p = strip_pos<N>(e, a.j0);
       if (p < m) {
-        if constexpr (park) {
-          v[s] = cmul(v[s], widen(L[2 * m + p]));
-        } else {
-          v[s] = cmul(v[s], phase(e));
-        }
+        v[s] = cmul(v[s], widen(L[2 * m + p]));
       }
     }
     __syncthreads();
@@ -170,20 +153,11 @@ __device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const L
 // SIMD), and at most 512 threads for P = 12 shapes (radix 3), which need more
 // registers: 168 VGPRs at 3 waves per SIMD (a few spills, measured faster
 // for batches of such lines than 2 waves without spills).
-#ifndef SOFFT_ROW_THREADS
-#define SOFFT_ROW_THREADS 1024
-#endif
-#ifndef SOFFT_COL_THREADS
-#define SOFFT_COL_THREADS 1024
-#endif
-constexpr int kRowThreads = SOFFT_ROW_THREADS;
-constexpr int kColThreads = SOFFT_COL_THREADS;
-#ifndef SOFFT_MIN_WAVES_WIDE
-#define SOFFT_MIN_WAVES_WIDE 3
-#endif
+constexpr int kRowThreads = 1024;
+constexpr int kColThreads = 1024;
 template <int N>
 constexpr int min_waves_per_simd() {
-  return Shape<N>::P == 4 ? 4 : SOFFT_MIN_WAVES_WIDE;
+  return Shape<N>::P == 4 ? 4 : 3;
 }
 // Threads per block: THREADS (P = 12 shapes at most 512, so that two waves
 // per SIMD leave them 256 VGPRs), and at least one whole line.
@@ -347,6 +321,17 @@ __device__ __forceinline__ void run_tiles(int ntiles, Body& body) {
   }
 }
 
+// Row tiles are assigned so that a tile and its mirror tile (rows n-1-j of
+// rows j) run on the same XCD (workgroups go round-robin over the 8 XCDs):
+// both read the same rows of the quadrant potential-phase table, which is
+// then fetched into one L2 only.  XCD x takes the tiles x K/2 + k and their
+// mirrors, K = ntiles/8; other tile counts keep the identity map.
+__device__ __forceinline__ int xcd_row_tile(int b, int ntiles) {
+  if (ntiles % 16 != 0 || b >= ntiles) return b;
+  const int half = ntiles / 16, x = b % 8, k = b / 8;
+  return k < half ? x * half + k : ntiles - 1 - (x * half + (k - half));
+}
+
 // Block LDS layout of the 2D passes: [line 0][line 1]...; a block holds
 // blockDim.x / TPL lines of a.lds_line elements.  FFT twiddles and CN
 // coefficients are read from global memory (they stay in the vector L1).
@@ -355,7 +340,6 @@ __device__ __forceinline__ void run_tiles(int ntiles, Body& body) {
 template <typename T, int N, bool PERSIST, bool UP = false>
 __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (kernel_waves<N, PERSIST>())) k_row_pass(PassArgs<T> a) {
   using X = xch_t<T>;
-  constexpr bool park = std::is_same<X, double>::value;
   constexpr int P = Shape<N>::P, TPL = N / P;
   extern __shared__ __align__(16) unsigned char smem[];
   cx<X>* lines = reinterpret_cast<cx<X>*>(smem);
@@ -366,7 +350,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
   const bool cn = a.do_pot && a.m > 0;
   const int64_t step = pass_step(a);
   auto body = [&](int tile) {
-    const int g = tile * lpb + l;
+    const int g = (PERSIST ? tile : xcd_row_tile(tile, a.ntiles)) * lpb + l;
     const bool live = g < nlines;
     const int gg = live ? g : 0;
     const int run = gg / a.ny, crow = gg - run * a.ny;
@@ -438,8 +422,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     if (a.do_pot) {
       // Rows outside the y-strip get both potential half-steps here (C_y is the
       // identity on them); rows on it get the first, the column pass the second.
-      // On the x-strip the phase waits in LDS (from 2m) across the CN, or is
-      // evaluated again after it when LDS holds FP32.
+      // On the x-strip the phase waits in LDS (from 2m) across the CN.
       // exp(-i U dt/2) = exp(-i V0 dt/2) exp(-i f x dt/2)
       const bool both = strip_pos_rt(crow, a.j0y, a.ny) >= a.my;
       const int m = a.m;
@@ -451,9 +434,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
         if (p < m) {
           v[s] = cmul(v[s], ph);
           L[p] = narrow<X>(v[s]);
-          if constexpr (park) {
-            if (both) L[2 * m + p] = ph;
-          }
+          if (both) L[2 * m + p] = ph;
         } else {
           v[s] = cmul(v[s], both ? cmul(ph, ph) : ph);
         }
@@ -465,13 +446,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
           const int p = strip_pos<N>(t + TPL * s, a.j0);
           if (p < m) {
             v[s] = 2.0 * widen(L[cn_result(m, a.levels) + p]) - v[s];
-            if (both) {
-              if constexpr (park) {
-                v[s] = cmul(v[s], widen(L[2 * m + p]));
-              } else {
-                v[s] = cmul(v[s], cmul(vps[s], expi(fh * xs[s], 0.0)));
-              }
-            }
+            if (both) v[s] = cmul(v[s], widen(L[2 * m + p]));
           }
         }
       }

@@ -12,7 +12,7 @@ import pytest
 
 from oracle import tdse as ot
 from paper_1505_06707_amd import workloads as wl
-from tests.helpers import CONTOURS, oracle_axis, rel_l2
+from tests.helpers import CONTOURS, oracle_axis, outgoing_state, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -224,3 +224,35 @@ def test_batch_mixed_contours_with_tfecs():
         err = rel_l2(out[i], o)
         print(f"   run {i} n={n} {kind}: rel L2 vs oracle {err:.2e}", flush=True)
         assert err < TOL64
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_large_shapes_against_oracle(dtype):
+    """Runs of 512^2, 768^2 and 1024^2 (two of each, launch shapes tuned as in
+    the benchmark, steps replayed from the graph) against the oracle, with
+    packets driven into the ECS strips of both axes."""
+    s = _sofft()
+    dt, nsteps = 0.05, 24
+    sizes = [512, 768, 1024, 512, 768, 1024]
+    problems, psi0, fs = [], [], []
+    for i, n in enumerate(sizes):
+        L = n * 0.2
+        problems.append(_problem(s, n, s.C64 if dtype == "c64" else s.C128))
+        ax = ot.Axis(n, L, R0=0.8 * L / 2)
+        psi0.append(outgoing_state(ax, ax, speed=2.0 + 0.5 * (i % 3), inset=1.5))
+        fs.append(wl.Pulse(E0=0.05 + 0.01 * i, omega=0.3, cycles=2).at_midpoints(0.0, dt, nsteps))
+    print(f"batch {dtype} runs {sizes} x {nsteps} steps, strips", flush=True)
+    cdt = np.complex64 if dtype == "c64" else np.complex128
+    b = s.Batch(problems)
+    b.set_graph_steps(8)
+    states = [torch.from_numpy(p.astype(cdt)).cuda() for p in psi0]
+    b.propagate(states, dt, nsteps, torch.from_numpy(np.stack(fs)).cuda(), norms=False)
+    torch.cuda.synchronize()
+    out = [t.cpu().numpy().astype(np.complex128) for t in states]
+    b.close()
+    for i in (0, 1, 2):
+        n = sizes[i]
+        o = _oracle(n, psi0[i], fs[i], dt)
+        err = rel_l2(out[i], o)
+        print(f"   run {i} n={n}: rel L2 vs oracle {err:.2e}", flush=True)
+        assert err < (TOL32 if dtype == "c64" else TOL64)

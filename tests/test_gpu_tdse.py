@@ -8,7 +8,7 @@ import pytest
 
 from oracle import tdse as ot
 from paper_1505_06707_amd import workloads as wl
-from tests.helpers import CONTOURS, oracle_axis, rel_l2
+from tests.helpers import CONTOURS, oracle_axis, outgoing_state, rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -245,3 +245,87 @@ def test_fp32_1d_error_against_fp64_oracle():
     err = rel_l2(g, o)
     print(f"   1D c64 4096 x 4000: rel L2 = {err:.3e}", flush=True)
     assert err < TOL32
+
+
+# ---------------------------------------------------------------- ECS strips
+# Packets started a few units inside R0 and moving outward put real amplitude
+# on the exterior strips, so the Crank-Nicolson solve of the remainder C
+# (Sec. II, Eq. C_FD and the CN formula) acts on data, at the line lengths the
+# full-size grids use: the row pass's PCR with several wavefronts per line
+# (512-, 768- and 1024-point rows) and the column pass's edge-slot CN.
+
+
+STRIP_SHAPES = [(1024, 16), (16, 1024), (512, 32), (32, 512), (768, 48), (48, 768), (384, 64)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("nx,ny", STRIP_SHAPES)
+def test_2d_parity_with_amplitude_on_the_strips(nx, ny, dtype):
+    s = _sofft()
+    print(f"2D strips {nx}x{ny} {dtype}", flush=True)
+    h = 0.2
+    Lx, Ly = nx * h, ny * h
+    R0x, R0y = 0.8 * Lx / 2, 0.8 * Ly / 2
+    ax, ay = ot.Axis(nx, Lx, R0=R0x), ot.Axis(ny, Ly, R0=R0y)
+    psi0 = outgoing_state(ax, ay)
+    f = wl.Pulse(E0=0.08, omega=0.3, cycles=2).at_midpoints(0.0, 0.05, 80)
+    args = (nx, ny, Lx, Ly, R0x, R0y, 0.5, "secs", 1.0, 0.64, psi0, 0.05, f)
+    o = oracle_2d(*args)
+    # the long axis's strips took real amplitude: part of the norm is gone
+    strip = (np.abs(ax.x)[None, :] > R0x) | (np.abs(ay.x)[:, None] > R0y)
+    assert np.linalg.norm(o[strip]) > 0.05 * np.linalg.norm(o)
+    assert np.linalg.norm(o) < 0.97 * np.linalg.norm(psi0)
+    g = run_gpu_2d(*args, dtype=s.C128 if dtype == "c128" else s.C64)
+    err = rel_l2(g, o)
+    print(f"   rel L2 = {err:.3e}", flush=True)
+    assert err < (TOL64 if dtype == "c128" else 1e-5)
+
+
+def test_2d_full_size_parity_amplitude_on_the_strips():
+    """The 1024^2 workload grid in the benchmark's launch configuration, with
+    packets driven into the x- and y-strips (40 steps)."""
+    c = wl.TDSE_2D
+    print("2D full grid 1024^2, strips, 40 steps", flush=True)
+    ax = ot.Axis(c.n, c.L, R0=c.R0)
+    psi0 = outgoing_state(ax, ax, speed=3.0, inset=2.0)
+    f = c.pulse.at_midpoints(0.0, c.dt, 40)
+    args = (c.n, c.n, c.L, c.L, c.R0, c.R0, c.theta, "secs", c.charge, c.a2, psi0, c.dt, f)
+    o = oracle_2d(*args)
+    strip = (np.abs(ax.x)[None, :] > c.R0) | (np.abs(ax.x)[:, None] > c.R0)
+    assert np.linalg.norm(o[strip]) > 0.1 * np.linalg.norm(o)
+    assert rel_l2(run_gpu_2d(*args), o) < TOL64
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_2d_full_workload_against_stored_oracle_checkpoints(dtype):
+    """The whole 2D workload (1024^2, 2000 steps of the pulse, packet seed 1)
+    against the FP64 oracle's state after 100, 500, 1000 and 2000 steps, stored
+    at 8192 seeded grid points with the squared norm of the whole state
+    (tests/golden/make_tdse_2d_1024_checkpoints.py, which calls only the
+    oracle).  complex128: relative L2 over the samples <= 1e-10; complex64
+    (FP32 storage, FP64 arithmetic on chip): <= 1e-5 at every checkpoint."""
+    import os
+    s = _sofft()
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "tdse_2d_1024_checkpoints.npz"))
+    c = wl.TDSE_2D
+    ax = ot.Axis(c.n, c.L, R0=c.R0)
+    psi0 = wl.gaussian_2d(ax.x, ax.x, **wl.packet_params(int(gold["packet_seed"])))
+    f = c.pulse.at_midpoints(0.0, c.dt, int(gold["steps"][-1]))
+    dt_ = s.C128 if dtype == "c128" else s.C64
+    plan = s.Plan([c.n, c.n], [c.L, c.L], R0=[c.R0, c.R0], theta=c.theta, charge=c.charge, a2=c.a2, dtype=dt_)
+    psi = _dev(psi0.astype(np.complex128 if dtype == "c128" else np.complex64))
+    fd = _dev(f)
+    tol = TOL64 if dtype == "c128" else TOL32
+    done = 0
+    for k, step in enumerate(gold["steps"]):
+        step = int(step)
+        print(f"2D 1024^2 {dtype}: steps {done}..{step}", flush=True)
+        plan.propagate(psi, c.dt, step - done, fd[done:step])
+        done = step
+        torch.cuda.synchronize()
+        got = psi.cpu().numpy().astype(np.complex128).ravel()[gold["index"]]
+        err = rel_l2(got, gold["samples"][k])
+        nerr = abs(plan.norm2(psi) - gold["norm2"][k]) / gold["norm2"][k]
+        print(f"   step {step}: rel L2 on samples {err:.3e}, norm^2 rel error {nerr:.3e}", flush=True)
+        assert err < tol and nerr < tol
+    plan.close()

@@ -80,3 +80,43 @@ def test_banded_cocg_reaches_the_dense_solution_2d():
     x, it, res = sse.cocg(op, f, rtol=1e-13)
     assert res <= 1e-13
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
+
+
+def _banded_kinetic_dense(axis, bands):
+    """K_a of Eq. K_l in the Fourier basis, block-diagonal over the bands, built
+    without the oracle's Toeplitz shortcut: Q = F diag(q^-2) F^dagger with the
+    dense F of Eq. Fmatrix, [K_l]_{nm} = 1/2 k_n k_m Q_{nm} inside a band."""
+    from oracle import grid
+    F = grid.dft_matrix(axis.n, axis.L)
+    Q = F @ np.diag(axis.q ** -2.0) @ F.conj().T
+    K = np.zeros((axis.n, axis.n), dtype=complex)
+    for b in bands:
+        idx = np.asarray(b)
+        K[np.ix_(idx, idx)] = 0.5 * np.outer(axis.k[idx], axis.k[idx]) * Q[np.ix_(idx, idx)]
+    return K
+
+
+@pytest.mark.parametrize("kind", [contour.SECS, contour.TFECS])
+def test_banded_preconditioner_inverts_its_own_operator(kind):
+    """P^-1 = F^-1 X^T (Lambda - E)^-1 X F is the exact inverse of
+    F^-1 K_a F - E with K_a assembled from the blocks K_l (Eqs. K_l,
+    PreconFFT_ECS).  Swapping X and X^T in the apply breaks this identity."""
+    rng = np.random.default_rng(21)
+    ax = tdse.Axis(64, 12.8, kind=kind, R0=3.5, theta=0.5)
+    ay = tdse.Axis(48, 9.6, kind=kind, R0=2.8, theta=0.5)
+    E = 0.65
+    op = sse.Operator((ax, ay), np.zeros((48, 64)), E)
+    Kx = _banded_kinetic_dense(ax, banded.bands(64))
+    Ky = _banded_kinetic_dense(ay, banded.bands(48))
+    v = rng.normal(size=(48, 64)) + 1j * rng.normal(size=(48, 64))
+    s = op._F(v)
+    Av = op._Finv(s @ Kx.T + Ky @ s) - E * v
+    P = banded.preconditioner(op)
+    assert np.linalg.norm(P(Av) - v) / np.linalg.norm(v) < 1e-11
+    # the same check with X and X^T swapped in the apply must fail
+    ab = [banded.AxisBands(ax), banded.AxisBands(ay)]
+    div = ab[0].lam[None, :] + ab[1].lam[:, None] - E
+    t = op._F(Av)
+    t = ab[0].apply_X(ab[1].apply_X(t, 0, transpose=True), 1, transpose=True)
+    t = ab[1].apply_X(ab[0].apply_X(t / div, 1), 0)
+    assert np.linalg.norm(op._Finv(t) - v) / np.linalg.norm(v) > 1e-3

@@ -464,3 +464,38 @@ def test_uniform_field_along_y_shifts_the_mean_momentum():
     ky = 2 * np.pi * np.fft.fftfreq(64, d=ay.h)
     py = np.sum(ky[:, None] * np.abs(spec) ** 2) / np.sum(np.abs(spec) ** 2)
     assert abs(py - (-f * tau * nst)) < 1e-10
+
+
+# ---- soft-core potential at complex coordinates (Sec. II: U(z(x), t))
+
+def test_softcore_hand_values():
+    """Values worked out by hand, without a square root routine:
+    V0(0) = -Zc/sqrt(a2); (1 + 2i)^2 = -3 + 4i and (1 - 2i)^2 = -3 - 4i, so on
+    the principal branch sqrt(-3 +- 4i) = 1 +- 2i and V0 = -1/(1 +- 2i) =
+    -(1 -+ 2i)/5; (0.8i)^2 + 0.64 = 0 removes the y term and a2."""
+    assert tdse.softcore(1.0, 2.0, np.array([0.0j]))[0] == pytest.approx(-2 ** -0.5, abs=3e-16)
+    assert tdse.softcore(1.0, 0.64, np.array([0.0j]), np.array([0.0j]))[0] == pytest.approx(-1.25, abs=1e-15)
+    assert tdse.softcore(3.0, 0.25, np.array([0.0j]))[0] == pytest.approx(-6.0, abs=1e-15)
+    zx = np.array([1 + 2j, 1 - 2j])
+    zy = np.array([0.8j, 0.8j])
+    got = tdse.softcore(1.0, 0.64, zx, zy)
+    assert np.max(np.abs(got - np.array([-0.2 + 0.4j, -0.2 - 0.4j]))) < 1e-15
+    # 1D with (2 + i)^2 = 3 + 4i and a2 = 2: sqrt(5 + 4i) is not simple, but
+    # (2 + 1i)^2 + (-6 + 0i) = -3 + 4i, so a2 = -6 reaches the same value
+    assert abs(tdse.softcore(2.0, -6.0, np.array([2 + 1j]))[0] - 2 * (-0.2 + 0.4j)) < 1e-15
+    # the other branch would give -V0: Re sqrt > 0 is what is fixed here
+    assert got[0].real < 0 and got[1].real < 0
+
+
+def test_softcore_on_the_real_axis_and_far_away():
+    """Interior nodes (q = 1, z = x) give the real -Zc/sqrt(x^2 + a2); far out
+    along the scaled contour (|z| >> a) V0 approaches -Zc/z (Re z > 0)."""
+    ax = _axis(256, 51.2, R0=20.0, theta=0.5)
+    inner = np.abs(ax.x) < 20.0
+    v = tdse.softcore(1.0, 2.0, ax.z)
+    x = ax.x[inner]
+    assert np.max(np.abs(v[inner].imag)) == 0.0
+    assert np.max(np.abs(v[inner].real * np.sqrt(x * x + 2.0) + 1.0)) < 1e-15
+    z = np.array([300.0 * np.exp(0.4j), 500.0 * np.exp(0.7j)])
+    w = tdse.softcore(1.0, 0.64, z)
+    assert np.max(np.abs(w * z + 1.0)) < 1e-5        # -1/z (1 - a2/(2 z^2) + ...)
