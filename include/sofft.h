@@ -18,8 +18,19 @@
  *  - The values held are those of the scaled function psi~(x) = sqrt(q(x))
  *    psi(z(x)) (Sec. II, Eq. psi_zx).
  *  - Device buffers passed in are owned by the caller; the library never frees
- *    or keeps them.  The plan owns its own small device tables (a few times n
- *    elements per axis) and frees them in sofft_plan_destroy.
+ *    them.  Ownership of device memory:
+ *      * a plan owns its small device tables (O(n) elements per axis: grid,
+ *        contour, twiddles, kinetic phases, Crank-Nicolson coefficients, and
+ *        for 2D complex128 plans the banded-preconditioner blocks), allocated
+ *        once by sofft_plan_create at their largest size and freed by
+ *        sofft_plan_destroy;
+ *      * every buffer of the size of a grid or larger (potential-phase table,
+ *        reduction partials, the stationary solver's vectors) lives in a
+ *        workspace the caller allocates and binds (sofft_workspace_size,
+ *        sofft_plan_bind; sofft_batch_workspace_size, sofft_batch_bind for
+ *        batches).  After sofft_plan_create no call allocates device memory
+ *        (the learned-correction object and batch creation aside: see there).
+ *    A call that needs more workspace than is bound returns SOFFT_EWORKSPACE.
  *  - Work is enqueued on the HIP stream given as `stream` (NULL = the default
  *    stream) and is asynchronous unless the call writes to host memory.
  *  - Errors: negative status codes; nothing has been enqueued when one is
@@ -41,6 +52,7 @@ typedef enum {
   SOFFT_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. grid length) */
   SOFFT_EHIP = -3,          /* HIP runtime error */
   SOFFT_ENOMEM = -4,        /* device allocation failed */
+  SOFFT_EWORKSPACE = -5,    /* no workspace bound, or smaller than the call needs */
   SOFFT_NOT_CONVERGED = 1,  /* solver hit maxit before rtol */
   SOFFT_BREAKDOWN = 2       /* COCG breakdown that a restart did not cure */
 } sofft_status;
@@ -91,8 +103,26 @@ int32_t sofft_version(void);
  * Returns SOFFT_EINVAL / SOFFT_EUNSUPPORTED / SOFFT_ENOMEM / SOFFT_EHIP. */
 sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out);
 
-/* Free the plan and its device tables (after the work using it has finished). */
+/* Free the plan and its device tables (after the work using it has finished).
+ * A bound workspace stays the caller's. */
 sofft_status sofft_plan_destroy(sofft_plan* plan);
+
+/* Bytes of device workspace the plan needs for sofft_propagate, sofft_norm2
+ * and, with n_energies > 0, for stationary solves and applications of up to
+ * n_energies energies at once (2D complex128 plans; SOFFT_EUNSUPPORTED
+ * otherwise).  About 16 bytes per grid point for propagation (the table of
+ * exp(-i V0 dt/2), room for a caller's V0), plus about 6 n_energies
+ * n_x n_y 16 bytes for solves.  Host only: nothing is enqueued. */
+sofft_status sofft_workspace_size(const sofft_plan* plan, int32_t n_energies, int64_t* bytes);
+
+/* Bind a caller-owned device workspace of `bytes` bytes (256-byte aligned, on
+ * the plan's device) to the plan; NULL unbinds.  The plan keeps the pointer
+ * and lays out its buffers in it; the memory must stay valid, and must not be
+ * used by anything else, while work enqueued on the plan can still run.
+ * Binding again (another or the same memory) makes the next propagation
+ * rebuild its potential-phase table.  Calls that need more than what is bound
+ * (sofft_workspace_size) return SOFFT_EWORKSPACE and enqueue nothing. */
+sofft_status sofft_plan_bind(sofft_plan* plan, void* workspace, int64_t bytes);
 
 /* Copy the n[axis] node coordinates x_j (Sec. II, Eq. DVRgrid) to host memory. */
 sofft_status sofft_grid_nodes(const sofft_plan* plan, int32_t axis, double* x_host);
@@ -133,11 +163,13 @@ sofft_status sofft_make_softcore(const sofft_plan* plan, double charge, double a
  * (nsteps doubles; may be NULL when there is no field).  In 2D,
  * K = (k_x^2 + k_y^2)/2 and e^{-iC dt} = CN(C_x) CN(C_y).  Neighbouring kinetic
  * half-steps of consecutive steps are applied as one full step, which is exact.
- * dt may be negative (backward propagation).  nsteps = 0 is a no-op. */
+ * dt may be negative (backward propagation).  nsteps = 0 is a no-op.  Needs
+ * the workspace of sofft_workspace_size(plan, 0) bound (SOFFT_EWORKSPACE). */
 sofft_status sofft_propagate(sofft_plan* plan, void* psi, double dt, int64_t nsteps,
                              const double* f_mid, void* stream);
 
-/* ||psi||^2 = sum |psi_j|^2 accumulated in FP64 (blocking: waits for the stream). */
+/* ||psi||^2 = sum |psi_j|^2 accumulated in FP64 (blocking: waits for the
+ * stream).  Its partial sums use the bound workspace. */
 sofft_status sofft_norm2(sofft_plan* plan, const void* psi, double* norm2_host, void* stream);
 
 /* Outcome of one energy of sofft_sse_solve. */
@@ -165,8 +197,8 @@ typedef struct {
  *   E_host  host, nE energies
  *   x_out   device, [nE][n_y][n_x], written
  *   stats   host, nE entries (may be NULL)
- * 2D complex128 plans only.  The plan allocates a workspace of about
- * 6 nE n_x n_y * 16 bytes on first use (kept until sofft_plan_destroy).
+ * 2D complex128 plans only.  The bound workspace must hold
+ * sofft_workspace_size(plan, nE) bytes (about 6 nE n_x n_y * 16).
  * Blocking: returns after the solve.  Returns SOFFT_OK when every energy met
  * rtol, else SOFFT_NOT_CONVERGED / SOFFT_BREAKDOWN (per energy in stats). */
 sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
@@ -175,7 +207,8 @@ sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_ener
 
 /* One application of the stationary matrix (op 0: w = A v, Eq. linsys) or of
  * the FFT preconditioner (op 1: w = P^-1 v, Eq. PreconFFT) at energy E, on
- * device vectors [n_y][n_x].  Asynchronous on the stream. */
+ * device vectors [n_y][n_x].  Needs the workspace of one energy
+ * (sofft_workspace_size(plan, 1)).  Asynchronous on the stream. */
 sofft_status sofft_sse_apply(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double field,
                              void* stream);
 
@@ -240,8 +273,7 @@ sofft_status sofft_band_tables(const sofft_problem* prob, int32_t axis, double* 
  *   eta_candidates  host, ncand shifts, finite and >= 0
  *   scratch_x       device, nE * ncand * n_x * n_y complex128, overwritten
  *   eta_out         host, nE entries, written with the chosen candidates
- * The plan's solver workspace grows to nE * ncand systems (kept until
- * sofft_plan_destroy).  Blocking.  SOFFT_OK unless an argument is bad
+ * The bound workspace must hold nE * ncand energies.  Blocking.  SOFFT_OK unless an argument is bad
  * (SOFFT_EINVAL) or a launch or allocation fails. */
 sofft_status sofft_sse_tune_shift(sofft_plan* plan, const void* f, const double* E_host, int32_t nE, double field,
                                   const double* eta_candidates, int32_t ncand, int32_t probe_iters, double rtol,
@@ -260,8 +292,20 @@ typedef struct sofft_batch sofft_batch;
 
 /* nrun problems (host array), all 2D and of one dtype; each must be valid for
  * sofft_plan_create.  The batch owns the tables of its distinct shapes, two
- * device pointer tables per shape, one stream and event per shape. */
+ * small device pointer tables and a step counter per shape (allocated here),
+ * one stream and event per shape. */
 sofft_status sofft_batch_create(const sofft_problem* probs, int32_t nrun, sofft_batch** out);
+
+/* Bytes of device workspace a batch needs: the potential-phase table of each
+ * distinct shape, per-run norm partial sums, and scratch states of the size
+ * of the largest shape's runs, on which the launch shapes are timed.  Host
+ * only. */
+sofft_status sofft_batch_workspace_size(const sofft_batch* b, int64_t* bytes);
+
+/* Bind a caller-owned device workspace to a batch (256-byte aligned; NULL
+ * unbinds), with the conditions of sofft_plan_bind.  sofft_batch_propagate
+ * returns SOFFT_EWORKSPACE when less than sofft_batch_workspace_size is bound. */
+sofft_status sofft_batch_bind(sofft_batch* b, void* workspace, int64_t bytes);
 
 /* Free the batch (after the work using it has finished). */
 sofft_status sofft_batch_destroy(sofft_batch* b);

@@ -56,7 +56,8 @@ struct sofft_batch {
   bool exec_field = false;
   hipEvent_t fork = nullptr;
   hipStream_t cap = nullptr;        // capture origin (the caller's stream may be the null stream)
-  DevBuf partials;                  // per-run norm partial sums
+  void* ws = nullptr;               // caller-owned workspace (sofft_batch_bind)
+  size_t ws_bytes = 0;
   std::vector<double> host_partials;
   std::vector<void*> staging;
 };
@@ -83,7 +84,6 @@ void destroy(sofft_batch* b) {
   }
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  dev_free(b->partials);
   delete b;
 }
 
@@ -96,6 +96,50 @@ sofft_status dev_alloc(DevBuf& d, size_t bytes) {
     return SOFFT_ENOMEM;
   }
   d.bytes = bytes;
+  return SOFFT_OK;
+}
+
+constexpr int kNormBlocksRun = 64;
+size_t r256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Layout of a batch's caller workspace: each class plan's workspace (its
+// potential-phase table), the per-run norm partial sums, then the scratch
+// states and pointer table the launch-shape timing runs on (the size of the
+// largest class's runs).
+struct BatchWs {
+  std::vector<size_t> cls_off, cls_bytes;
+  size_t partials = 0, tune = 0, tune_ptrs = 0, total = 0;
+};
+BatchWs batch_ws_layout(const sofft_batch* b) {
+  BatchWs L;
+  size_t off = 0, tune = 0, nrmax = 0;
+  const size_t elem = b->dtype == SOFFT_C128 ? 16 : 8;
+  for (const BatchClass& c : b->cls) {
+    const size_t bytes = plan_ws_layout(plan_of(c.plan), 0).total;
+    L.cls_off.push_back(off);
+    L.cls_bytes.push_back(bytes);
+    off += r256(bytes);
+    tune = std::max(tune, c.runs.size() * size_t(c.points) * elem);
+    nrmax = std::max(nrmax, c.runs.size());
+  }
+  L.partials = off;
+  off += r256(size_t(b->nrun) * kNormBlocksRun * sizeof(double));
+  L.tune = off;
+  off += r256(tune);
+  L.tune_ptrs = off;
+  off += r256(nrmax * sizeof(void*));
+  L.total = off;
+  return L;
+}
+
+sofft_status batch_ws_check(const sofft_batch* b, BatchWs* out) {
+  BatchWs L = batch_ws_layout(b);
+  if (!b->ws || b->ws_bytes < L.total) {
+    set_error("the batch needs a bound workspace of " + std::to_string(L.total) +
+              " bytes (sofft_batch_workspace_size, sofft_batch_bind); bound: " + std::to_string(b->ws ? b->ws_bytes : 0));
+    return SOFFT_EWORKSPACE;
+  }
+  *out = std::move(L);
   return SOFFT_OK;
 }
 
@@ -115,30 +159,22 @@ PassRequest request(const BatchClass& c, bool row, bool half, int do_pot, double
 // Time one pass of a class with each candidate launch shape on scratch states
 // and keep the fastest.  Candidates: 256, 512 and 1024 threads per block, each
 // with one block per tile and with a persistent grid of the resident blocks.
-sofft_status tune_class(BatchClass& c, double dt, hipStream_t s) {
+sofft_status tune_class(BatchClass& c, double dt, void* scratch, void* scratch_ptrs, hipStream_t s) {
   Plan& p = plan_of(c.plan);
   const size_t elem = p.prob.dtype == SOFFT_C128 ? 16 : 8;
   const int nr = int(c.runs.size());
-  DevBuf scratch, sptr;
-  sofft_status st = dev_alloc(scratch, size_t(nr) * size_t(c.points) * elem);
-  if (st == SOFFT_OK) st = dev_alloc(sptr, size_t(nr) * sizeof(void*));
-  if (st != SOFFT_OK) {
-    dev_free(scratch);
-    return st;
-  }
+  sofft_status st;
   std::vector<void*> hp(nr);
-  for (int r = 0; r < nr; ++r) hp[r] = static_cast<char*>(scratch.p) + size_t(r) * size_t(c.points) * elem;
+  for (int r = 0; r < nr; ++r) hp[r] = static_cast<char*>(scratch) + size_t(r) * size_t(c.points) * elem;
   int cus = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   auto fail = [&](sofft_status code) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    dev_free(scratch);
-    dev_free(sptr);
     return code;
   };
-  if (hipMemcpy(sptr.p, hp.data(), nr * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemsetAsync(scratch.p, 0, size_t(nr) * size_t(c.points) * elem, s) != hipSuccess ||
+  if (hipMemcpy(scratch_ptrs, hp.data(), nr * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemsetAsync(scratch, 0, size_t(nr) * size_t(c.points) * elem, s) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     set_error("batch tuning: HIP set-up failed");
@@ -147,7 +183,7 @@ sofft_status tune_class(BatchClass& c, double dt, hipStream_t s) {
   for (int pass = 0; pass < 2; ++pass) {
     const bool row = pass == 0;
     PassRequest rq = request(c, row, false, 1, dt, false);
-    rq.runs = static_cast<void* const*>(sptr.p);
+    rq.runs = static_cast<void* const*>(scratch_ptrs);
     float best = 1e30f;
     PassLaunch pick{};
     for (int threads : {256, 512, 1024}) {
@@ -325,6 +361,34 @@ sofft_status sofft_batch_create(const sofft_problem* probs, int32_t nrun, sofft_
   return SOFFT_OK;
 }
 
+sofft_status sofft_batch_workspace_size(const sofft_batch* b, int64_t* bytes) {
+  if (!b || !bytes) {
+    set_error("bad argument to sofft_batch_workspace_size");
+    return SOFFT_EINVAL;
+  }
+  *bytes = int64_t(batch_ws_layout(b).total);
+  return SOFFT_OK;
+}
+
+sofft_status sofft_batch_bind(sofft_batch* b, void* workspace, int64_t bytes) {
+  if (!b || bytes < 0 || (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)) {
+    set_error("bad argument to sofft_batch_bind (the workspace must be 256-byte aligned)");
+    return SOFFT_EINVAL;
+  }
+  const BatchWs L = batch_ws_layout(b);
+  const bool fits = workspace && size_t(bytes) >= L.total;
+  b->ws = workspace;
+  b->ws_bytes = workspace ? size_t(bytes) : 0;
+  for (size_t k = 0; k < b->cls.size(); ++k) {
+    Plan& p = plan_of(b->cls[k].plan);
+    p.ws = fits ? static_cast<char*>(workspace) + L.cls_off[k] : nullptr;
+    p.ws_bytes = fits ? L.cls_bytes[k] : 0;
+    p.vphase_ht = __builtin_nan("");
+  }
+  drop_graph(b);   // the captured passes read tables in the previous workspace
+  return SOFFT_OK;
+}
+
 sofft_status sofft_batch_destroy(sofft_batch* b) {
   if (b) destroy(b);
   return SOFFT_OK;
@@ -386,6 +450,8 @@ sofft_status sofft_batch_propagate(sofft_batch* b, void* const* psi, double dt, 
     }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   sofft_status st;
+  BatchWs WL;
+  if ((st = batch_ws_check(b, &WL)) != SOFFT_OK) return st;
   const bool field = f_mid != nullptr;
   bool tables_changed = false;
   for (BatchClass& c : b->cls) {
@@ -417,7 +483,9 @@ sofft_status sofft_batch_propagate(sofft_batch* b, void* const* psi, double dt, 
   if (nsteps > 0) {
     for (BatchClass& c : b->cls)
       if (!c.tuned) {
-        if ((st = tune_class(c, dt, s)) != SOFFT_OK) return st;
+        if ((st = tune_class(c, dt, static_cast<char*>(b->ws) + WL.tune, static_cast<char*>(b->ws) + WL.tune_ptrs,
+                             s)) != SOFFT_OK)
+          return st;
         drop_graph(b);
       }
     // opening K_y/2
@@ -447,9 +515,8 @@ sofft_status sofft_batch_propagate(sofft_batch* b, void* const* psi, double dt, 
       if ((st = launch_pass(plan_of(c.plan), request(c, true, true, 0, dt, false), s)) != SOFFT_OK) return st;
   }
   if (norm2_host) {
-    constexpr int kBlocks = 64;
-    if ((st = dev_alloc(b->partials, size_t(b->nrun) * kBlocks * sizeof(double))) != SOFFT_OK) return st;
-    double* part = static_cast<double*>(b->partials.p);
+    constexpr int kBlocks = kNormBlocksRun;
+    double* part = reinterpret_cast<double*>(static_cast<char*>(b->ws) + WL.partials);
     int off = 0;
     for (BatchClass& c : b->cls) {
       const int nr = int(c.runs.size());

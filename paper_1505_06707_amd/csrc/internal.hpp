@@ -90,12 +90,14 @@ struct Timing {
 struct Plan {
   sofft_problem prob{};
   Axis ax[2];
-  DevBuf partials;   // reduction scratch (norms)
   std::vector<double> host_partials;
   Timing timing;
-  DevBuf sse_ws, sse_E, sse_eta;   // stationary-solver workspace, energies, divisor shifts
-  // exp(-i V0 dt/2) on the grid for the dt in vphase_ht = dt/2 (NaN: none)
-  DevBuf vphase;
+  // Caller-owned device workspace (sofft_plan_bind); every buffer of O(grid)
+  // size lives there, laid out by plan_ws_layout.
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // The workspace's potential-phase table holds exp(-i V0 dt/2) for the dt in
+  // vphase_ht = dt/2 (NaN: not built, or the workspace changed since).
   double vphase_ht = __builtin_nan("");
   // A caller's potential U = V0 + f W (device, caller-owned): V0 complex
   // [ny][nx] in place of the soft-core, W real [ny][nx] in place of x; null:
@@ -104,11 +106,33 @@ struct Plan {
   const double* user_w = nullptr;
 };
 
+// Layout of a plan's caller workspace: the potential-phase table (the whole
+// grid, complex128: room for a caller's V0), the norm partial sums, then the
+// stationary solver's region for n_energies energies (none for 0).  Regions
+// start on 256-byte boundaries.
+struct WsLayout {
+  size_t vphase = 0, partials = 0, solver = 0;
+  size_t solver_bytes = 0;
+  size_t total = 0;
+};
+constexpr int kNormBlocks = 1024;
+WsLayout plan_ws_layout(const Plan& p, int n_energies);
+// Checks that the bound workspace holds the layout for n_energies energies
+// (SOFFT_EWORKSPACE with a message naming the size otherwise).
+sofft_status plan_ws_check(const Plan& p, int n_energies, WsLayout* L);
+inline char* ws_at(const Plan& p, size_t off) { return static_cast<char*>(p.ws) + off; }
+// Bytes of the stationary solver's region for nE energies (sse.hip).
+size_t sse_solver_bytes(const Plan& p, int nE);
+
 // Table builders (plan.hip).
 sofft_status build_axis(Axis& a, int64_t n, double L, double R0, double theta, int contour);
-sofft_status upload_static(Axis& a);
+sofft_status upload_static(Axis& a, bool bands);
 sofft_status ensure_dt(Axis& a, double dt);
 void free_axis(Axis& a);
+// Device tables of a plan are reserved once, in sofft_plan_create, at their
+// largest size (dev_reserve); later calls only copy into them (dev_upload
+// fails if the copy would not fit, which would be a library bug).
+sofft_status dev_reserve(DevBuf& b, size_t bytes);
 sofft_status dev_upload(DevBuf& b, const void* host, size_t bytes);
 // Raise a kernel's dynamic LDS limit to `limit` bytes, once per kernel (the
 // attribute belongs to the function; the call is made the first time a launch

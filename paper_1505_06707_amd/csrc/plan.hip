@@ -25,15 +25,23 @@ sofft_status raise_lds_limit(const void* kernel, size_t limit) {
   return SOFFT_OK;
 }
 
+sofft_status dev_reserve(DevBuf& b, size_t bytes) {
+  if (b.p && b.bytes >= bytes) return SOFFT_OK;
+  dev_free(b);
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    b.p = nullptr;
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    return SOFFT_ENOMEM;
+  }
+  b.bytes = bytes;
+  return SOFFT_OK;
+}
+
 sofft_status dev_upload(DevBuf& b, const void* host, size_t bytes) {
-  if (b.p && b.bytes != bytes) dev_free(b);
-  if (!b.p) {
-    if (hipMalloc(&b.p, bytes) != hipSuccess) {
-      b.p = nullptr;
-      set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
-      return SOFFT_ENOMEM;
-    }
-    b.bytes = bytes;
+  if (!b.p || b.bytes < bytes) {
+    set_error("internal: device table of " + std::to_string(b.bytes) + " bytes cannot take " +
+              std::to_string(bytes));
+    return SOFFT_EUNSUPPORTED;
   }
   SOFFT_HIP_TRY(hipMemcpy(b.p, host, bytes, hipMemcpyHostToDevice));
   return SOFFT_OK;
@@ -43,6 +51,31 @@ void dev_free(DevBuf& b) {
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
+}
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+WsLayout plan_ws_layout(const Plan& p, int n_energies) {
+  WsLayout L;
+  const size_t npts = size_t(p.ax[0].n) * (p.prob.ndim == 2 ? size_t(p.ax[1].n) : 1);
+  L.vphase = 0;
+  L.partials = round256(npts * sizeof(cx<double>));
+  L.solver = L.partials + round256(kNormBlocks * sizeof(double));
+  L.solver_bytes = n_energies > 0 ? sse_solver_bytes(p, n_energies) : 0;
+  L.total = L.solver + round256(L.solver_bytes);
+  return L;
+}
+
+sofft_status plan_ws_check(const Plan& p, int n_energies, WsLayout* out) {
+  const WsLayout L = plan_ws_layout(p, n_energies);
+  if (!p.ws || p.ws_bytes < L.total) {
+    set_error("the plan needs a bound workspace of " + std::to_string(L.total) + " bytes" +
+              (n_energies > 0 ? " for " + std::to_string(n_energies) + " energies" : std::string()) +
+              " (sofft_workspace_size, sofft_plan_bind); bound: " + std::to_string(p.ws ? p.ws_bytes : 0));
+    return SOFFT_EWORKSPACE;
+  }
+  if (out) *out = L;
+  return SOFFT_OK;
 }
 
 bool supported_length(int64_t n) {
@@ -248,7 +281,33 @@ static std::vector<cx<T>> to_cx(const std::vector<zc>& v) {
   return o;
 }
 
-sofft_status upload_static(Axis& a) {
+// Every device table of an axis at its largest size: the tables that depend
+// on dt (kinetic phases, PCR coefficients for at most ceil(log2 m) levels) are
+// refilled in place when dt changes, so no call after sofft_plan_create
+// allocates device memory.  Band tables only for plans that can solve.
+static sofft_status reserve_axis(Axis& a, bool bands) {
+  const size_t c = sizeof(cx<double>), n = size_t(a.n), m = size_t(std::max<int64_t>(a.m, 1));
+  int maxlev = 1;
+  while ((int64_t(1) << maxlev) < a.m) ++maxlev;
+  sofft_status st;
+  for (auto req : {std::make_pair(&a.tw64, n * c), std::make_pair(&a.x_dev, n * sizeof(double)),
+                   std::make_pair(&a.z_dev, n * c), std::make_pair(&a.cstrip64, 3 * m * c),
+                   std::make_pair(&a.kin_full64, n * c), std::make_pair(&a.kin_half64, n * c),
+                   std::make_pair(&a.alpha64, size_t(maxlev) * m * c), std::make_pair(&a.gamma64, size_t(maxlev) * m * c),
+                   std::make_pair(&a.binv64, m * c)})
+    if ((st = dev_reserve(*req.first, req.second)) != SOFFT_OK) return st;
+  if (bands)
+    for (auto req : {std::make_pair(&a.band_lam, n * c), std::make_pair(&a.band_xr, size_t(kBandMax) * n * c),
+                     std::make_pair(&a.band_xc, size_t(kBandMax) * n * c),
+                     std::make_pair(&a.band_start, n * sizeof(int32_t)),
+                     std::make_pair(&a.band_width, n * sizeof(int32_t))})
+      if ((st = dev_reserve(*req.first, req.second)) != SOFFT_OK) return st;
+  return SOFFT_OK;
+}
+
+sofft_status upload_static(Axis& a, bool bands) {
+  sofft_status st0 = reserve_axis(a, bands);
+  if (st0 != SOFFT_OK) return st0;
   // Stage twiddle tables of the line FFT (layout in line_fft.hpp), evaluated
   // in long double and rounded.
   const ShapeInfo sh = shape_info(a.n);
@@ -449,7 +508,7 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
       set_error("ECS strip of " + std::to_string(pl->ax[d].m) + " nodes exceeds 256 per axis in 2D; increase R0");
       st = SOFFT_EUNSUPPORTED;
     }
-    if (st == SOFFT_OK) st = upload_static(pl->ax[d]);
+    if (st == SOFFT_OK) st = upload_static(pl->ax[d], p.ndim == 2 && p.dtype == SOFFT_C128);
     if (st != SOFFT_OK) {
       for (int e = 0; e < 2; ++e) free_axis(pl->ax[e]);
       delete pl;
@@ -463,12 +522,31 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
 sofft_status sofft_plan_destroy(sofft_plan* plan) {
   if (!plan) return SOFFT_OK;
   for (int d = 0; d < 2; ++d) free_axis(plan->ax[d]);
-  dev_free(plan->partials);
-  dev_free(plan->sse_ws);
-  dev_free(plan->sse_E);
-  dev_free(plan->sse_eta);
-  dev_free(plan->vphase);
   delete plan;
+  return SOFFT_OK;
+}
+
+sofft_status sofft_workspace_size(const sofft_plan* plan, int32_t n_energies, int64_t* bytes) {
+  if (!plan || !bytes || n_energies < 0) {
+    set_error("bad argument to sofft_workspace_size");
+    return SOFFT_EINVAL;
+  }
+  if (n_energies > 0 && (plan->prob.ndim != 2 || plan->prob.dtype != SOFFT_C128)) {
+    set_error("the stationary solver works on 2D complex128 plans");
+    return SOFFT_EUNSUPPORTED;
+  }
+  *bytes = int64_t(plan_ws_layout(*plan, n_energies).total);
+  return SOFFT_OK;
+}
+
+sofft_status sofft_plan_bind(sofft_plan* plan, void* workspace, int64_t bytes) {
+  if (!plan || bytes < 0 || (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)) {
+    set_error("bad argument to sofft_plan_bind (the workspace must be 256-byte aligned)");
+    return SOFFT_EINVAL;
+  }
+  plan->ws = workspace;
+  plan->ws_bytes = workspace ? size_t(bytes) : 0;
+  plan->vphase_ht = __builtin_nan("");   // the phase table is rebuilt in the new memory
   return SOFFT_OK;
 }
 

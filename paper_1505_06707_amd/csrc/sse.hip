@@ -92,6 +92,8 @@ struct SseArgs {
   cx<double>* part_rzo;        // [nE][nblk_row]: r^T z_old
   int* active;                 // [nE]: energies the network corrects this round
   double* lp_scale;            // [nE]: rms of r
+  double* E_dev;               // [nE] workspace copies of the energies and shifts
+  double* eta_dev;
 };
 
 enum RowMode : int { kRowIter = 0, kRowTrue = 1 };          // K1: input p (updated) or x
@@ -774,33 +776,48 @@ static SseLauncher sse_launcher(int64_t nx, int64_t ny) {
   return nullptr;
 }
 
-// Workspace: five vectors per energy, U on the grid, partial sums, scalars.
+// Solver region of the workspace: five vectors per energy, U on the grid,
+// partial sums, scalars, the energies and divisor shifts.
+struct SseSizes {
+  size_t vec, bytes_vec;
+  int llx, lly, nbr, nbc;
+};
+static SseSizes sse_sizes(const Plan& p) {
+  const Axis& X = p.ax[0];
+  const Axis& Y = p.ax[1];
+  SseSizes z;
+  z.vec = size_t(X.n) * Y.n;
+  z.bytes_vec = z.vec * sizeof(cx<double>);
+  z.llx = int(std::max<int64_t>(sse_lds_elems(X.n), 64));
+  z.lly = int(std::max<int64_t>(sse_lds_elems(Y.n), 64));
+  const int lpr = sse_lpb(X.n, z.llx, kSseRowThreads), lpc = sse_lpb(Y.n, z.lly, sse_col_threads(Y.n));
+  z.nbr = int((Y.n + lpr - 1) / lpr);
+  z.nbc = int((X.n + lpc - 1) / lpc);
+  return z;
+}
+
+static size_t r256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t sse_solver_bytes(const Plan& p, int nE) {
+  const SseSizes z = sse_sizes(p);
+  return 5 * r256(z.bytes_vec * nE) + r256(z.bytes_vec) + r256(sizeof(double) * nE * z.nbr) +
+         2 * r256(sizeof(cx<double>) * nE * z.nbr) + r256(sizeof(cx<double>) * nE * z.nbc) +
+         r256(sizeof(CocgScalars) * nE) + r256(sizeof(int) * nE) + 3 * r256(sizeof(double) * nE);
+}
+
 static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipStream_t s) {
   const Axis& X = p.ax[0];
   const Axis& Y = p.ax[1];
-  const size_t vec = size_t(X.n) * Y.n;
-  const int llx = int(std::max<int64_t>(sse_lds_elems(X.n), 64));
-  const int lly = int(std::max<int64_t>(sse_lds_elems(Y.n), 64));
-  const int lpr = sse_lpb(X.n, llx, kSseRowThreads), lpc = sse_lpb(Y.n, lly, sse_col_threads(Y.n));
-  const int nbr = int((Y.n + lpr - 1) / lpr);
-  const int nbc = int((X.n + lpc - 1) / lpc);
-  const size_t bytes_vec = vec * sizeof(cx<double>);
-  const size_t need = 5 * bytes_vec * nE + bytes_vec + size_t(nE) * nbr * (sizeof(double) + 2 * sizeof(cx<double>)) +
-                      size_t(nE) * nbc * sizeof(cx<double>) + size_t(nE) * sizeof(CocgScalars) +
-                      size_t(nE) * (sizeof(int) + sizeof(double)) + 8192;
-  if (!p.sse_ws.p || p.sse_ws.bytes < need) {
-    dev_free(p.sse_ws);
-    if (hipMalloc(&p.sse_ws.p, need) != hipSuccess) {
-      p.sse_ws.p = nullptr;
-      set_error("hipMalloc of the solver workspace (" + std::to_string(need) + " bytes) failed");
-      return SOFFT_ENOMEM;
-    }
-    p.sse_ws.bytes = need;
-  }
-  char* q = static_cast<char*>(p.sse_ws.p);
+  WsLayout WL;
+  sofft_status st0 = plan_ws_check(p, nE, &WL);
+  if (st0 != SOFFT_OK) return st0;
+  const SseSizes z = sse_sizes(p);
+  const size_t vec = z.vec, bytes_vec = z.bytes_vec;
+  const int llx = z.llx, lly = z.lly, nbr = z.nbr, nbc = z.nbc;
+  char* q = ws_at(p, WL.solver);
   auto take = [&](size_t b) {
     char* r = q;
-    q += (b + 255) / 256 * 256;
+    q += r256(b);
     return r;
   };
   a.nx = int(X.n);
@@ -821,6 +838,8 @@ static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipSt
   a.part_rzo = reinterpret_cast<cx<double>*>(take(sizeof(cx<double>) * nE * nbr));
   a.active = reinterpret_cast<int*>(take(sizeof(int) * nE));
   a.lp_scale = reinterpret_cast<double*>(take(sizeof(double) * nE));
+  a.E_dev = reinterpret_cast<double*>(take(sizeof(double) * nE));
+  a.eta_dev = reinterpret_cast<double*>(take(sizeof(double) * nE));
   a.nblk_row = nbr;
   a.nblk_col = nbc;
   a.twx = static_cast<const cx<double>*>(X.tw64.p);
@@ -857,21 +876,6 @@ static sofft_status sse_check_plan(const Plan& p) {
   return SOFFT_OK;
 }
 
-// Copy n doubles from the host into a plan-owned device buffer (grown as needed).
-static sofft_status upload_doubles(DevBuf& b, const double* host, int n, hipStream_t s) {
-  if (!b.p || b.bytes < sizeof(double) * n) {
-    dev_free(b);
-    if (hipMalloc(&b.p, sizeof(double) * n) != hipSuccess) {
-      b.p = nullptr;
-      set_error("hipMalloc failed");
-      return SOFFT_ENOMEM;
-    }
-    b.bytes = sizeof(double) * n;
-  }
-  SOFFT_HIP_TRY(hipMemcpyAsync(b.p, host, sizeof(double) * n, hipMemcpyHostToDevice, s));
-  return SOFFT_OK;
-}
-
 // The tables of the banded preconditioner of both axes into the solver's arguments.
 static sofft_status use_bands(Plan& p, SseArgs& a) {
   sofft_status st;
@@ -904,21 +908,12 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
   a.x = static_cast<cx<double>*>(x_out);
   a.f = static_cast<const cx<double>*>(f);
   a.f_per_energy = f_per_energy;
-  // energies
-  if (!p.sse_E.p || p.sse_E.bytes < sizeof(double) * nE) {
-    dev_free(p.sse_E);
-    if (hipMalloc(&p.sse_E.p, sizeof(double) * nE) != hipSuccess) {
-      p.sse_E.p = nullptr;
-      set_error("hipMalloc failed");
-      return SOFFT_ENOMEM;
-    }
-    p.sse_E.bytes = sizeof(double) * nE;
-  }
-  SOFFT_HIP_TRY(hipMemcpyAsync(p.sse_E.p, E_host, sizeof(double) * nE, hipMemcpyHostToDevice, s));
-  a.E = static_cast<const double*>(p.sse_E.p);
+  // energies and shifts, in the solver region
+  SOFFT_HIP_TRY(hipMemcpyAsync(a.E_dev, E_host, sizeof(double) * nE, hipMemcpyHostToDevice, s));
+  a.E = a.E_dev;
   if (eta_host) {
-    if ((st = upload_doubles(p.sse_eta, eta_host, nE, s)) != SOFFT_OK) return st;
-    a.eta = static_cast<const double*>(p.sse_eta.p);
+    SOFFT_HIP_TRY(hipMemcpyAsync(a.eta_dev, eta_host, sizeof(double) * nE, hipMemcpyHostToDevice, s));
+    a.eta = a.eta_dev;
   }
   if (banded && (st = use_bands(p, a)) != SOFFT_OK) return st;
   SseLauncher L = sse_launcher(p.ax[0].n, p.ax[1].n);
@@ -1060,20 +1055,11 @@ sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double
   if (st != SOFFT_OK) return st;
   SseArgs a{};
   if ((st = sse_prepare(p, 1, field, a, s)) != SOFFT_OK) return st;
-  if (!p.sse_E.p || p.sse_E.bytes < sizeof(double)) {
-    dev_free(p.sse_E);
-    if (hipMalloc(&p.sse_E.p, sizeof(double)) != hipSuccess) {
-      p.sse_E.p = nullptr;
-      set_error("hipMalloc failed");
-      return SOFFT_ENOMEM;
-    }
-    p.sse_E.bytes = sizeof(double);
-  }
-  SOFFT_HIP_TRY(hipMemcpyAsync(p.sse_E.p, &E, sizeof(double), hipMemcpyHostToDevice, s));
-  a.E = static_cast<const double*>(p.sse_E.p);
+  SOFFT_HIP_TRY(hipMemcpyAsync(a.E_dev, &E, sizeof(double), hipMemcpyHostToDevice, s));
+  a.E = a.E_dev;
   if (eta != 0.0) {
-    if ((st = upload_doubles(p.sse_eta, &eta, 1, s)) != SOFFT_OK) return st;
-    a.eta = static_cast<const double*>(p.sse_eta.p);
+    SOFFT_HIP_TRY(hipMemcpyAsync(a.eta_dev, &eta, sizeof(double), hipMemcpyHostToDevice, s));
+    a.eta = a.eta_dev;
   }
   if (banded && (st = use_bands(p, a)) != SOFFT_OK) return st;
   CocgScalars c{};

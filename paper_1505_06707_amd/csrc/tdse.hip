@@ -321,17 +321,6 @@ __device__ __forceinline__ void run_tiles(int ntiles, Body& body) {
   }
 }
 
-// Row tiles are assigned so that a tile and its mirror tile (rows n-1-j of
-// rows j) run on the same XCD (workgroups go round-robin over the 8 XCDs):
-// both read the same rows of the quadrant potential-phase table, which is
-// then fetched into one L2 only.  XCD x takes the tiles x K/2 + k and their
-// mirrors, K = ntiles/8; other tile counts keep the identity map.
-__device__ __forceinline__ int xcd_row_tile(int b, int ntiles) {
-  if (ntiles % 16 != 0 || b >= ntiles) return b;
-  const int half = ntiles / 16, x = b % 8, k = b / 8;
-  return k < half ? x * half + k : ntiles - 1 - (x * half + (k - half));
-}
-
 // Block LDS layout of the 2D passes: [line 0][line 1]...; a block holds
 // blockDim.x / TPL lines of a.lds_line elements.  FFT twiddles and CN
 // coefficients are read from global memory (they stay in the vector L1).
@@ -350,7 +339,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
   const bool cn = a.do_pot && a.m > 0;
   const int64_t step = pass_step(a);
   auto body = [&](int tile) {
-    const int g = (PERSIST ? tile : xcd_row_tile(tile, a.ntiles)) * lpb + l;
+    const int g = tile * lpb + l;
     const bool live = g < nlines;
     const int gg = live ? g : 0;
     const int run = gg / a.ny, crow = gg - run * a.ny;
@@ -744,7 +733,8 @@ static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   a.x = static_cast<const double*>(p.ax[0].x_dev.p);
   a.zx = static_cast<const cx<double>*>(p.ax[0].z_dev.p);
   a.zy = p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p) : nullptr;
-  a.vph = p.vphase_ht == 0.5 * dt ? static_cast<const cx<double>*>(p.vphase.p) : nullptr;
+  a.vph = p.vphase_ht == 0.5 * dt ? reinterpret_cast<const cx<double>*>(ws_at(p, plan_ws_layout(p, 0).vphase))
+                                   : nullptr;
   a.vfull = p.user_v0 != nullptr;
   a.w = p.user_w;
   a.j0 = int(A.j0);
@@ -936,36 +926,29 @@ static sofft_status occupancy_n(bool row, int n, int lds_line, int threads, int*
 
 // The table of exp(-i V0 dt/2) for this dt (plans with a potential): one
 // quadrant for the soft-core, the whole grid for a caller's V0.
+// The table of exp(-i V0 dt/2) for this dt (plans with a potential), in the
+// plan's workspace: one quadrant for the soft-core, the whole grid for a
+// caller's V0.
 sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
   if (changed) *changed = false;
+  WsLayout L;
+  sofft_status st = plan_ws_check(p, 0, &L);
+  if (st != SOFFT_OK) return st;
   if ((p.prob.charge == 0.0 && !p.user_v0) || p.vphase_ht == 0.5 * dt) return SOFFT_OK;
   const bool full = p.user_v0 != nullptr;
   const int ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
   const int hx = int(p.ax[0].n) / 2, hy = p.prob.ndim == 2 ? ny / 2 : 1;
   const size_t n = full ? size_t(p.ax[0].n) * ny : size_t(hx) * hy;
-  const size_t bytes = n * sizeof(cx<double>);
-  if (p.vphase.p && p.vphase.bytes < bytes) dev_free(p.vphase);
-  if (!p.vphase.p) {
-    if (hipMalloc(&p.vphase.p, bytes) != hipSuccess) {
-      p.vphase.p = nullptr;
-      set_error("hipMalloc of the potential-phase table failed");
-      return SOFFT_ENOMEM;
-    }
-    p.vphase.bytes = bytes;
-  }
+  cx<double>* table = reinterpret_cast<cx<double>*>(ws_at(p, L.vphase));
   if (full) {
-    k_vphase_user<<<unsigned((n + 255) / 256), 256, 0, s>>>(static_cast<cx<double>*>(p.vphase.p),
-                                                          static_cast<const cx<double>*>(p.user_v0), n, 0.5 * dt);
-    SOFFT_HIP_TRY(hipGetLastError());
-    p.vphase_ht = 0.5 * dt;
-    if (changed) *changed = true;
-    return SOFFT_OK;
+    k_vphase_user<<<unsigned((n + 255) / 256), 256, 0, s>>>(table, static_cast<const cx<double>*>(p.user_v0), n,
+                                                          0.5 * dt);
+  } else {
+    k_vphase<<<unsigned((n + 255) / 256), 256, 0, s>>>(table, hx, hy, static_cast<const cx<double>*>(p.ax[0].z_dev.p),
+                                                       p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p)
+                                                                        : nullptr,
+                                                       p.prob.charge, p.prob.a2, 0.5 * dt);
   }
-  k_vphase<<<unsigned((n + 255) / 256), 256, 0, s>>>(static_cast<cx<double>*>(p.vphase.p), hx, hy,
-                                                     static_cast<const cx<double>*>(p.ax[0].z_dev.p),
-                                                     p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p)
-                                                                      : nullptr,
-                                                     p.prob.charge, p.prob.a2, 0.5 * dt);
   SOFFT_HIP_TRY(hipGetLastError());
   p.vphase_ht = 0.5 * dt;
   if (changed) *changed = true;
@@ -1088,18 +1071,12 @@ sofft_status launch_propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, 
 }
 
 sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s) {
+  WsLayout L;
+  sofft_status st = plan_ws_check(p, 0, &L);
+  if (st != SOFFT_OK) return st;
   int64_t n = p.ax[0].n * (p.prob.ndim == 2 ? p.ax[1].n : 1);
-  const int blocks = int(std::min<int64_t>(1024, (n + 255) / 256));
-  if (!p.partials.p || p.partials.bytes < blocks * sizeof(double)) {
-    dev_free(p.partials);
-    if (hipMalloc(&p.partials.p, 1024 * sizeof(double)) != hipSuccess) {
-      p.partials.p = nullptr;
-      set_error("hipMalloc failed");
-      return SOFFT_ENOMEM;
-    }
-    p.partials.bytes = 1024 * sizeof(double);
-  }
-  double* part = static_cast<double*>(p.partials.p);
+  const int blocks = int(std::min<int64_t>(kNormBlocks, (n + 255) / 256));
+  double* part = reinterpret_cast<double*>(ws_at(p, L.partials));
   if (p.prob.dtype == SOFFT_C128)
     k_norm2<double><<<blocks, 256, 0, s>>>(static_cast<const cx<double>*>(psi), n, part);
   else

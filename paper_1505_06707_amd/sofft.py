@@ -17,7 +17,7 @@ C128, C64 = 0, 1
 SECS, SHARP, ECS_OFF, TFECS = 0, 1, 2, 3
 
 _STATUS = {0: "SOFFT_OK", -1: "SOFFT_EINVAL", -2: "SOFFT_EUNSUPPORTED", -3: "SOFFT_EHIP",
-           -4: "SOFFT_ENOMEM", 1: "SOFFT_NOT_CONVERGED", 2: "SOFFT_BREAKDOWN"}
+           -4: "SOFFT_ENOMEM", -5: "SOFFT_EWORKSPACE", 1: "SOFFT_NOT_CONVERGED", 2: "SOFFT_BREAKDOWN"}
 
 
 class SofftError(RuntimeError):
@@ -58,6 +58,8 @@ _SIGS = {
     "sofft_version": (ctypes.c_int32, []),
     "sofft_plan_create": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_void_p)]),
     "sofft_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sofft_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "sofft_plan_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "sofft_grid_nodes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "sofft_strip_length": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "sofft_propagate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
@@ -89,6 +91,8 @@ _SIGS = {
                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "sofft_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sofft_batch_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "sofft_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "sofft_batch_propagate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_batch_set_graph_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -168,6 +172,15 @@ def _dev_ptr(t, dtype, numel, name):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def device_workspace(nbytes, device="cuda"):
+    """A caller-owned device workspace of at least nbytes bytes, 256-byte
+    aligned: (the torch tensor that owns it, aligned pointer)."""
+    import torch
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    ptr = (t.data_ptr() + 255) // 256 * 256
+    return t, ptr
+
+
 class Plan:
     """A libsofft plan: grid, contour and potential of Sec. II, on the current device."""
 
@@ -194,6 +207,31 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib().sofft_plan_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
+        self._ws = None
+        self._ws_energies = -1
+        self.ensure_workspace(0)
+
+    def workspace_size(self, n_energies=0):
+        """Bytes of device workspace for propagation and solves of n_energies energies."""
+        b = ctypes.c_int64()
+        _check(lib().sofft_workspace_size(self._h, int(n_energies), ctypes.byref(b)))
+        return b.value
+
+    def ensure_workspace(self, n_energies=0):
+        """Allocate (with torch) and bind a workspace large enough for
+        n_energies energies, if the bound one is smaller."""
+        if n_energies <= self._ws_energies:
+            return
+        nbytes = self.workspace_size(n_energies)
+        if self._ws is not None:
+            import torch
+            torch.cuda.current_stream().synchronize()   # work on the old workspace has finished
+            _check(lib().sofft_plan_bind(self._h, ctypes.c_void_p(0), 0))
+            self._ws = None
+        t, ptr = device_workspace(nbytes)
+        _check(lib().sofft_plan_bind(self._h, ctypes.c_void_p(ptr), nbytes))
+        self._ws = t
+        self._ws_energies = int(n_energies)
 
     @property
     def numel(self):
@@ -208,6 +246,7 @@ class Plan:
         if getattr(self, "_h", None):
             lib().sofft_plan_destroy(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -269,6 +308,7 @@ class Plan:
         eta != 0 shifts the preconditioner's divisor to K - E - i eta; banded
         selects the preconditioner of Eq. PreconFFT_ECS."""
         import torch
+        self.ensure_workspace(1)
         ptr = _dev_ptr(v, torch.complex128, self.numel, "v")
         if out is None:
             out = torch.empty_like(v)
@@ -293,6 +333,7 @@ class Plan:
         import torch
         E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
         nE = len(E)
+        self.ensure_workspace(nE)
         per = 1 if f.numel() == nE * self.numel and nE > 1 else 0
         fptr = _dev_ptr(f, torch.complex128, self.numel * (nE if per else 1), "f")
         if out is None:
@@ -322,6 +363,7 @@ class Plan:
         E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
         cand = np.ascontiguousarray(np.asarray(candidates, dtype=np.float64).ravel())
         nE, nc = len(E), len(cand)
+        self.ensure_workspace(nE * nc)
         fptr = _dev_ptr(f, torch.complex128, self.numel, "f")
         scratch = torch.empty((nE * nc,) + self.shape, dtype=torch.complex128, device=f.device)
         sptr = _dev_ptr(scratch, torch.complex128, nE * nc * self.numel, "scratch")
@@ -339,6 +381,7 @@ class Plan:
         import torch
         E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
         nE = len(E)
+        self.ensure_workspace(nE)
         per = 1 if f.numel() == nE * self.numel and nE > 1 else 0
         fptr = _dev_ptr(f, torch.complex128, self.numel * (nE if per else 1), "f")
         if out is None:
@@ -410,11 +453,16 @@ class Batch:
         self._h = h
         self.problems = list(problems)
         self.dtype = problems[0].dtype
+        b = ctypes.c_int64()
+        _check(lib().sofft_batch_workspace_size(self._h, ctypes.byref(b)))
+        self._ws, ptr = device_workspace(b.value)
+        _check(lib().sofft_batch_bind(self._h, ctypes.c_void_p(ptr), b.value))
 
     def close(self):
         if getattr(self, "_h", None):
             lib().sofft_batch_destroy(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -522,6 +570,7 @@ class LearnedCorrection:
         if len(E) != n:
             raise ValueError("one energy per pair is needed")
         losses = np.zeros(epochs, dtype=np.float64)
+        plan.ensure_workspace(1)
         _check(lib().sofft_lp_train(self._h, plan._h, _dev_ptr(r, torch.complex128, r.numel(), "r"),
                                     _dev_ptr(e, torch.complex128, r.numel(), "e"),
                                     E.ctypes.data_as(ctypes.c_void_p), n, int(epochs), int(batch), float(lr),

@@ -70,3 +70,12 @@ def test_null_arguments_are_rejected():
     assert L.sofft_norm2(None, None, None, None) == -1
     assert L.sofft_set_potential(None, None, None) == -1
     assert L.sofft_make_softcore(None, 1.0, 1.0, None, None) == -1
+
+
+def test_workspace_calls_reject_null_arguments():
+    L = sofft.lib()
+    n = ctypes.c_int64()
+    assert L.sofft_workspace_size(None, 0, ctypes.byref(n)) == -1
+    assert L.sofft_plan_bind(None, None, 0) == -1
+    assert L.sofft_batch_workspace_size(None, ctypes.byref(n)) == -1
+    assert L.sofft_batch_bind(None, None, 0) == -1
