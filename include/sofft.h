@@ -168,6 +168,22 @@ sofft_status sofft_make_softcore(const sofft_plan* plan, double charge, double a
 sofft_status sofft_propagate(sofft_plan* plan, void* psi, double dt, int64_t nsteps,
                              const double* f_mid, void* stream);
 
+/* sofft_propagate for callers that cannot allocate or bind device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same steps and kernels, with the one scratch buffer of a
+ * propagation, the table of exp(-i V0 dt/2), in a static device array of
+ * 8 MiB that the library holds on each GPU it runs on until the process ends
+ * (no workspace needs to be bound; nothing is allocated by the call).  Every
+ * call rebuilds the table there, so calls that overlap on one GPU (several
+ * streams or host threads) race and must be serialised by the caller.  A
+ * plan whose table exceeds 8 MiB (a caller's V0 on more than 2^19 grid
+ * points; the soft-core table, a quarter of the grid, always fits) returns
+ * SOFFT_EUNSUPPORTED.  The first call for a new dt copies the plan's
+ * dt-dependent tables synchronously (make it outside a graph capture).
+ * Results are bit-identical to sofft_propagate. */
+sofft_status sofft_propagate_static(sofft_plan* plan, void* psi, double dt, int64_t nsteps,
+                                    const double* f_mid, void* stream);
+
 /* ||psi||^2 = sum |psi_j|^2 accumulated in FP64 (blocking: waits for the
  * stream).  Its partial sums use the bound workspace. */
 sofft_status sofft_norm2(sofft_plan* plan, const void* psi, double* norm2_host, void* stream);

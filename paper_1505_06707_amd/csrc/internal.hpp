@@ -167,16 +167,19 @@ struct PassRequest {
 };
 
 // Launchers (tdse.hip).
-sofft_status launch_propagate_1d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
-                                 hipStream_t s);
-sofft_status launch_propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
-                                 hipStream_t s);
+// Propagation (1D or 2D) with the phase table in the plan's workspace, or in
+// the library's static device scratch (no allocation, no workspace).
+sofft_status launch_propagate(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid, hipStream_t s);
+sofft_status launch_propagate_static(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
+                                     hipStream_t s);
+size_t vphase_bytes(const Plan& p);
 sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s);
 // V0 = -charge / sqrt(sum z^2 + a2) on the plan's grid into out (complex, [ny][nx]).
 sofft_status launch_softcore(const Plan& p, double charge, double a2, void* out, hipStream_t s);
 sofft_status launch_pass(Plan& p, const PassRequest& rq, hipStream_t s);
 // Build or refresh the potential-phase table of a plan for dt (enqueued on s).
-sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed);
+sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed,
+                           const cx<double>** table = nullptr);
 sofft_status pass_residency(const Plan& p, bool row, int threads, int* blocks_per_cu, int* block_threads);
 // *counter += delta by one device thread (graph-safe step offsets).
 sofft_status launch_step_add(int64_t* counter, int64_t delta, bool set, hipStream_t s);

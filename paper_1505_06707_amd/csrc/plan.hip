@@ -579,9 +579,21 @@ sofft_status sofft_propagate(sofft_plan* plan, void* psi, double dt, int64_t nst
     sofft_status st = ensure_dt(plan->ax[d], dt);
     if (st != SOFFT_OK) return st;
   }
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return plan->prob.ndim == 1 ? launch_propagate_1d(*plan, psi, dt, nsteps, f_mid, s)
-                              : launch_propagate_2d(*plan, psi, dt, nsteps, f_mid, s);
+  return launch_propagate(*plan, psi, dt, nsteps, f_mid, reinterpret_cast<hipStream_t>(stream));
+}
+
+sofft_status sofft_propagate_static(sofft_plan* plan, void* psi, double dt, int64_t nsteps, const double* f_mid,
+                                    void* stream) {
+  if (!plan || !psi || nsteps < 0 || !std::isfinite(dt)) {
+    set_error("bad argument to sofft_propagate_static");
+    return SOFFT_EINVAL;
+  }
+  if (nsteps == 0) return SOFFT_OK;
+  for (int d = 0; d < plan->prob.ndim; ++d) {
+    sofft_status st = ensure_dt(plan->ax[d], dt);
+    if (st != SOFFT_OK) return st;
+  }
+  return launch_propagate_static(*plan, psi, dt, nsteps, f_mid, reinterpret_cast<hipStream_t>(stream));
 }
 
 sofft_status sofft_set_potential(sofft_plan* plan, const void* v0, const double* w) {

@@ -9,6 +9,8 @@
 // the loop apply the opening/closing K_y/2 and K_x/2.
 // 1D: one workgroup keeps the whole line in registers/LDS for all steps.
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "line_fft.hpp"
 #include "potential.hpp"
@@ -719,7 +721,7 @@ static int64_t lds_elems_for(int64_t n) {
 }
 
 template <typename T>
-static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
+static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt, const cx<double>* vph) {
   Axis& A = p.ax[axis];
   PassArgs<T> a{};
   a.psi = static_cast<cx<T>*>(psi);
@@ -733,8 +735,7 @@ static PassArgs<T> axis_args(Plan& p, int axis, void* psi, double dt) {
   a.x = static_cast<const double*>(p.ax[0].x_dev.p);
   a.zx = static_cast<const cx<double>*>(p.ax[0].z_dev.p);
   a.zy = p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p) : nullptr;
-  a.vph = p.vphase_ht == 0.5 * dt ? reinterpret_cast<const cx<double>*>(ws_at(p, plan_ws_layout(p, 0).vphase))
-                                   : nullptr;
+  a.vph = vph;
   a.vfull = p.user_v0 != nullptr;
   a.w = p.user_w;
   a.j0 = int(A.j0);
@@ -926,20 +927,20 @@ static sofft_status occupancy_n(bool row, int n, int lds_line, int threads, int*
 
 // The table of exp(-i V0 dt/2) for this dt (plans with a potential): one
 // quadrant for the soft-core, the whole grid for a caller's V0.
-// The table of exp(-i V0 dt/2) for this dt (plans with a potential), in the
-// plan's workspace: one quadrant for the soft-core, the whole grid for a
-// caller's V0.
-sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
-  if (changed) *changed = false;
-  WsLayout L;
-  sofft_status st = plan_ws_check(p, 0, &L);
-  if (st != SOFFT_OK) return st;
-  if ((p.prob.charge == 0.0 && !p.user_v0) || p.vphase_ht == 0.5 * dt) return SOFFT_OK;
+// Bytes of the table of exp(-i V0 dt/2): one quadrant for the soft-core, the
+// whole grid for a caller's V0; 0 when the plan has no potential.
+size_t vphase_bytes(const Plan& p) {
+  if (p.prob.charge == 0.0 && !p.user_v0) return 0;
+  const size_t nx = size_t(p.ax[0].n), ny = p.prob.ndim == 2 ? size_t(p.ax[1].n) : 1;
+  return (p.user_v0 ? nx * ny : (nx / 2) * (p.prob.ndim == 2 ? ny / 2 : 1)) * sizeof(cx<double>);
+}
+
+// Write the table of exp(-i V0 dt/2) of the plan into `table` (vphase_bytes).
+static sofft_status build_vphase(const Plan& p, double dt, cx<double>* table, hipStream_t s) {
   const bool full = p.user_v0 != nullptr;
   const int ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
   const int hx = int(p.ax[0].n) / 2, hy = p.prob.ndim == 2 ? ny / 2 : 1;
   const size_t n = full ? size_t(p.ax[0].n) * ny : size_t(hx) * hy;
-  cx<double>* table = reinterpret_cast<cx<double>*>(ws_at(p, L.vphase));
   if (full) {
     k_vphase_user<<<unsigned((n + 255) / 256), 256, 0, s>>>(table, static_cast<const cx<double>*>(p.user_v0), n,
                                                           0.5 * dt);
@@ -950,6 +951,22 @@ sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
                                                        p.prob.charge, p.prob.a2, 0.5 * dt);
   }
   SOFFT_HIP_TRY(hipGetLastError());
+  return SOFFT_OK;
+}
+
+// The plan's table of exp(-i V0 dt/2) in its workspace, built once per dt (and
+// per binding); *table is null when the plan has no potential.
+sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed, const cx<double>** table) {
+  if (changed) *changed = false;
+  if (table) *table = nullptr;
+  WsLayout L;
+  sofft_status st = plan_ws_check(p, 0, &L);
+  if (st != SOFFT_OK) return st;
+  if (vphase_bytes(p) == 0) return SOFFT_OK;
+  cx<double>* t = reinterpret_cast<cx<double>*>(ws_at(p, L.vphase));
+  if (table) *table = t;
+  if (p.vphase_ht == 0.5 * dt) return SOFFT_OK;
+  if ((st = build_vphase(p, dt, t, s)) != SOFFT_OK) return st;
   p.vphase_ht = 0.5 * dt;
   if (changed) *changed = true;
   return SOFFT_OK;
@@ -957,11 +974,9 @@ sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed) {
 
 template <typename T>
 static sofft_status propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
-                                 hipStream_t s) {
-  sofft_status st0 = ensure_vphase(p, dt, s, nullptr);
-  if (st0 != SOFFT_OK) return st0;
-  PassArgs<T> ra = axis_args<T>(p, 0, psi, dt);
-  PassArgs<T> ca = axis_args<T>(p, 1, psi, dt);
+                                 const cx<double>* vph, hipStream_t s) {
+  PassArgs<T> ra = axis_args<T>(p, 0, psi, dt, vph);
+  PassArgs<T> ca = axis_args<T>(p, 1, psi, dt, vph);
   ra.f_mid = ca.f_mid = f_mid;
   const cx<double>* kxf = static_cast<const cx<double>*>(p.ax[0].kin_full64.p);
   const cx<double>* kxh = static_cast<const cx<double>*>(p.ax[0].kin_half64.p);
@@ -990,9 +1005,13 @@ static sofft_status propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, 
 sofft_status launch_pass(Plan& p, const PassRequest& rq, hipStream_t s) {
   const int axis = rq.row ? 0 : 1;
   const Axis& A = p.ax[axis];
+  // the class plan's table, built by ensure_vphase for this dt
+  const cx<double>* vph = vphase_bytes(p) && p.vphase_ht == 0.5 * rq.dt
+                              ? reinterpret_cast<const cx<double>*>(ws_at(p, plan_ws_layout(p, 0).vphase))
+                              : nullptr;
   const cx<double>* kin = static_cast<const cx<double>*>(rq.half_kinetic ? A.kin_half64.p : A.kin_full64.p);
   if (p.prob.dtype == SOFFT_C128) {
-    PassArgs<double> a = axis_args<double>(p, axis, nullptr, rq.dt);
+    PassArgs<double> a = axis_args<double>(p, axis, nullptr, rq.dt, vph);
     a.runs = reinterpret_cast<cx<double>* const*>(rq.runs);
     a.f_runs = rq.f_runs;
     a.nruns = rq.nruns;
@@ -1002,7 +1021,7 @@ sofft_status launch_pass(Plan& p, const PassRequest& rq, hipStream_t s) {
     a.kin = kin;
     return pass_n<double>(rq.row, a, rq.cfg, s, rq.timing);
   }
-  PassArgs<float> a = axis_args<float>(p, axis, nullptr, rq.dt);
+  PassArgs<float> a = axis_args<float>(p, axis, nullptr, rq.dt, vph);
   a.runs = reinterpret_cast<cx<float>* const*>(rq.runs);
   a.f_runs = rq.f_runs;
   a.nruns = rq.nruns;
@@ -1043,10 +1062,8 @@ static sofft_status tdse1d(Plan& p, PassArgs<T> a, int64_t nsteps, hipStream_t s
 
 template <typename T>
 static sofft_status propagate_1d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
-                                 hipStream_t s) {
-  sofft_status st0 = ensure_vphase(p, dt, s, nullptr);
-  if (st0 != SOFFT_OK) return st0;
-  PassArgs<T> a = axis_args<T>(p, 0, psi, dt);
+                                 const cx<double>* vph, hipStream_t s) {
+  PassArgs<T> a = axis_args<T>(p, 0, psi, dt, vph);
   a.f_mid = f_mid;
   switch (p.ax[0].n) {
     case 2048: return tdse1d<T, 2048>(p, a, nsteps, s);
@@ -1058,16 +1075,74 @@ static sofft_status propagate_1d(Plan& p, void* psi, double dt, int64_t nsteps, 
   return SOFFT_EUNSUPPORTED;
 }
 
-sofft_status launch_propagate_1d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
-                                 hipStream_t s) {
-  return p.prob.dtype == SOFFT_C128 ? propagate_1d<double>(p, psi, dt, nsteps, f_mid, s)
-                                    : propagate_1d<float>(p, psi, dt, nsteps, f_mid, s);
+// Propagation with the potential-phase table `vph` (null: no potential).
+static sofft_status propagate_with(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
+                                   const cx<double>* vph, hipStream_t s) {
+  const bool c128 = p.prob.dtype == SOFFT_C128;
+  if (p.prob.ndim == 1)
+    return c128 ? propagate_1d<double>(p, psi, dt, nsteps, f_mid, vph, s)
+                : propagate_1d<float>(p, psi, dt, nsteps, f_mid, vph, s);
+  return c128 ? propagate_2d<double>(p, psi, dt, nsteps, f_mid, vph, s)
+              : propagate_2d<float>(p, psi, dt, nsteps, f_mid, vph, s);
 }
 
-sofft_status launch_propagate_2d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
-                                 hipStream_t s) {
-  return p.prob.dtype == SOFFT_C128 ? propagate_2d<double>(p, psi, dt, nsteps, f_mid, s)
-                                    : propagate_2d<float>(p, psi, dt, nsteps, f_mid, s);
+sofft_status launch_propagate(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid, hipStream_t s) {
+  const cx<double>* vph = nullptr;
+  sofft_status st = ensure_vphase(p, dt, s, nullptr, &vph);
+  if (st != SOFFT_OK) return st;
+  return propagate_with(p, psi, dt, nsteps, f_mid, vph, s);
+}
+
+// ------------------------------------------------ propagation without allocation
+// For callers that cannot allocate (graph capture, serving loops): the
+// potential-phase table, the only scratch memory of a propagation, lives in a
+// file-scope device array of kStaticScratchBytes that each GPU holds for the
+// life of the process.  Its address on a device comes from
+// hipGetSymbolAddress, taken once per device with that device current; host
+// code uses only that address.  Every call rebuilds the table (the array keeps
+// whatever the last call on the GPU wrote), so calls that overlap on one GPU
+// race.
+constexpr size_t kStaticScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static sofft_status static_scratch(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> per_device;
+  int dev = -1;
+  SOFFT_HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (int(per_device.size()) <= dev) per_device.resize(dev + 1, nullptr);
+  if (!per_device[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress of the static scratch failed: ") + hipGetErrorString(e));
+      return SOFFT_EHIP;
+    }
+    per_device[dev] = ptr;
+  }
+  *out = per_device[dev];
+  return SOFFT_OK;
+}
+
+sofft_status launch_propagate_static(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
+                                     hipStream_t s) {
+  const size_t need = vphase_bytes(p);
+  if (need > kStaticScratchBytes) {
+    set_error("the potential-phase table of this plan needs " + std::to_string(need) +
+              " bytes, more than the " + std::to_string(kStaticScratchBytes) +
+              " bytes of static scratch: use sofft_propagate with a bound workspace");
+    return SOFFT_EUNSUPPORTED;
+  }
+  cx<double>* vph = nullptr;
+  if (need) {
+    void* base = nullptr;
+    sofft_status st = static_scratch(&base);
+    if (st != SOFFT_OK) return st;
+    vph = static_cast<cx<double>*>(base);
+    if ((st = build_vphase(p, dt, vph, s)) != SOFFT_OK) return st;
+  }
+  return propagate_with(p, psi, dt, nsteps, f_mid, vph, s);
 }
 
 sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s) {

@@ -64,6 +64,8 @@ _SIGS = {
     "sofft_strip_length": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
     "sofft_propagate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "sofft_propagate_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
+                                              ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_norm2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.c_void_p]),
     "sofft_set_potential": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
