@@ -137,6 +137,72 @@ def fp32_vs_oracle_checkpoints(sofft, wl, torch):
     return out
 
 
+def gpu_tdse3d(sofft, wl, torch, steps=20, reps=5, device_warmup_s=0.3):
+    """The 3D workload (256^3, h = 0.4): per dtype the median of `reps`
+    HIP-event timed runs of `steps` steps, the per-launch durations of the
+    kinetic and strip passes, and the error against the FP64 oracle's stored
+    checkpoints (steps 25/50/100, 8192 sampled points and the norm)."""
+    c = wl.TDSE_3D
+    gold_path = os.path.join(ROOT, "tests", "golden", "tdse_3d_256_checkpoints.npz")
+    gold = np.load(gold_path) if os.path.exists(gold_path) else None
+    seed = int(gold["packet_seed"]) if gold is not None else 3
+    out = {"workload": f"3D {c.n}^3, h = {c.h}, SECS, soft-core a2 = {c.a2}, pulse along x, dt = {c.dt}"}
+    npts = c.n ** 3
+    for name, dt_ in (("c128", sofft.C128), ("c64", sofft.C64)):
+        S = 16 if dt_ == sofft.C128 else 8
+        plan = sofft.Plan([c.n] * 3, [c.L] * 3, R0=[c.R0] * 3, theta=c.theta, charge=c.charge, a2=c.a2, dtype=dt_)
+        x = plan.nodes(0)
+        cdt = np.complex128 if dt_ == sofft.C128 else np.complex64
+        psi0 = torch.from_numpy(wl.gaussian_3d(x, x, x, **wl.packet_params_3d(seed)).astype(cdt)).cuda()
+        nf = max(steps, 100)
+        f = torch.from_numpy(c.pulse.at_midpoints(0.0, c.dt, nf)).cuda()
+        spare = psi0.clone()
+        t_end = time.perf_counter() + device_warmup_s
+        while time.perf_counter() < t_end:
+            plan.propagate(spare, c.dt, 5, f[:5])
+            torch.cuda.synchronize()
+        del spare
+        ev = []
+        stream = torch.cuda.current_stream()
+        for _ in range(reps):
+            psi = psi0.clone()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            plan.propagate(psi, c.dt, steps, f[:steps], stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ev.append(e0.elapsed_time(e1) / 1e3)
+        psi = psi0.clone()
+        plan.timing(True)
+        plan.propagate(psi, c.dt, steps, f[:steps], stream=stream)
+        kin = plan.timing_read(sofft.KERNEL_3D_KINETIC)
+        strip = plan.timing_read(sofft.KERNEL_3D_STRIP)
+        plan.timing(False)
+        t = float(np.median(ev))
+        kin_us = kin[0] / kin[1] * 1e3
+        row = {"us_per_step": t / steps * 1e6, "value": npts * steps / t, "unit": "grid-point-steps/s",
+               "kinetic_pass_us": kin_us, "strip_pass_us": strip[0] / strip[1] * 1e3 if strip[1] else None,
+               "kinetic_pass_frac": 2 * S * npts / (kin_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+               "step_frac_6S": 6 * S * npts / (t / steps) / 1e9 / HBM_PEAK_GBS}
+        if gold is not None:
+            psi = psi0.clone()
+            done, errs = 0, {}
+            for k, step in enumerate(gold["steps"]):
+                step = int(step)
+                plan.propagate(psi, c.dt, step - done, f[done:step])
+                done = step
+                torch.cuda.synchronize()
+                got = psi.cpu().numpy().astype(np.complex128).ravel()[gold["index"]]
+                want = gold["samples"][k]
+                errs[str(step)] = {"rel_l2_samples": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+                                   "norm2_rel_err": float(abs(plan.norm2(psi) - gold["norm2"][k]) / gold["norm2"][k])}
+            row["vs_fp64_oracle"] = errs
+        plan.close()
+        out[name] = row
+    return out
+
+
 def gpu_tdse1d(sofft, wl, torch):
     """The 1D workload: 4096 points, 4000 steps in one workgroup (state in LDS/registers)."""
     c = wl.TDSE_1D
@@ -442,6 +508,7 @@ def main():
     ap.add_argument("--pcg-energies", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-1d", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -520,6 +587,17 @@ def main():
         log(f"  {tdse1d['time_s'] * 1e3:.1f} ms, {tdse1d['steps_per_s']:.0f} steps/s "
             f"({tdse1d['us_per_step']:.1f} us/step)")
 
+    tdse3d = None
+    if not args.no_3d:
+        log("TDSE 3D 256^3 (c128, c64)")
+        tdse3d = gpu_tdse3d(sofft, wl, torch, device_warmup_s=args.device_warmup_ms / 1e3)
+        for k in ("c128", "c64"):
+            r = tdse3d[k]
+            log(f"  {k}: {r['us_per_step']:.0f} us/step, {r['value'] / 1e9:.2f} G grid-point-steps/s, kinetic pass "
+                f"{r['kinetic_pass_us']:.0f} us ({100 * r['kinetic_pass_frac']:.0f}% of HBM peak)"
+                + (f", vs oracle {max(v['rel_l2_samples'] for v in r['vs_fp64_oracle'].values()):.1e}"
+                   if "vs_fp64_oracle" in r else ""))
+
     pcg = None
     if not args.no_pcg:
         log("SSE 512^2 batched COCG to 1e-8")
@@ -586,6 +664,7 @@ def main():
         "cpu_baseline": cpu,
         "fp32": fp32,
         "tdse_1d": tdse1d,
+        "tdse_3d": tdse3d,
         "pcg": pcg,
         "batch": batch,
         "learned": learned,

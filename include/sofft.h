@@ -13,7 +13,8 @@
  *  - Grid (Sec. II, Eq. DVRgrid): on a box of length L per axis the nodes are
  *    the cell centres x_j = -L/2 + h (j + 1/2), h = L/n, j = 0..n-1.
  *  - Arrays are complex, interleaved (re, im), in device memory, row-major with
- *    x the fast axis: psi[j_y * n_x + j_x].  Element type: double2 for
+ *    x the fast axis: psi[(j_z * n_y + j_y) * n_x + j_x] (the z and y terms
+ *    only in 3D and 2D).  Element type: double2 for
  *    SOFFT_C128 plans, float2 for SOFFT_C64 plans.
  *  - The values held are those of the scaled function psi~(x) = sqrt(q(x))
  *    psi(z(x)) (Sec. II, Eq. psi_zx).
@@ -71,15 +72,15 @@ typedef enum { SOFFT_SECS = 0, SOFFT_SHARP = 1, SOFFT_ECS_OFF = 2, SOFFT_TFECS =
 
 /* The problem statement of Sec. II/III: grid, ECS radius and angle, and the
  * static part of U.  U(x, t) = V0(z(x)) + f(t) x with the soft-core Coulomb
- * V0 = -charge / sqrt(z_x^2 [+ z_y^2] + a2) evaluated on the complex contour
+ * V0 = -charge / sqrt(z_x^2 [+ z_y^2 [+ z_z^2]] + a2) evaluated on the complex contour
  * (principal branch) and the dipole term f(t) x at the real coordinate x
  * (polarisation along x).  charge = 0 switches V0 off. */
 typedef struct {
-  int32_t ndim;      /* 1 or 2 */
+  int32_t ndim;      /* 1, 2 or 3 */
   int32_t dtype;     /* sofft_dtype of psi */
-  int64_t n[2];      /* nodes per axis: n[0] = n_x (fast), n[1] = n_y (2D only) */
-  double L[2];       /* box length per axis */
-  double R0[2];      /* ECS radius per axis, 0 < R0 < L/2 (ignored if contour off) */
+  int64_t n[3];      /* nodes per axis: n[0] = n_x (fast), n[1] = n_y, n[2] = n_z (slowest) */
+  double L[3];       /* box length per axis */
+  double R0[3];      /* ECS radius per axis, 0 < R0 < L/2 (ignored if contour off) */
   double theta;      /* ECS angle, 0 < theta < pi/2 (SECS, sharp); alpha > 0 (TFECS) */
   int32_t contour;   /* sofft_contour */
   double charge;     /* soft-core strength (>= 0) */
@@ -97,9 +98,13 @@ int32_t sofft_version(void);
 /* Build a plan: grid, momenta, contour tables q, z, the ECS remainder
  * C = K_s - K_FD (Sec. II, Eqs. C_FD, Ks_FD, K_FD, periodic stencils) and FFT
  * twiddles, and copy them to the current device.  Supported n per axis:
- * 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024 (1D and 2D) and 2048,
- * 4096 (1D only).  The ECS strip (nodes where C is non-zero) may hold at most
- * half of the nodes of an axis, and at most 256 nodes per axis in 2D.
+ * 16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024 (1D and 2D), 2048,
+ * 4096 (1D only), 16, 32, 64, 128, 256, 512 (3D).  The ECS strip (nodes where
+ * C is non-zero) may hold at most half of the nodes of an axis, and at most
+ * 256 nodes per axis in 2D and 3D.  3D: the paper is 1D and names the
+ * many-dimensional case as its next step; the step is read separably,
+ * K = (k_x^2 + k_y^2 + k_z^2)/2 and e^{-iC dt} = CN(C_x) CN(C_y) CN(C_z).
+ * The stationary solver and batches take 2D plans only.
  * Returns SOFFT_EINVAL / SOFFT_EUNSUPPORTED / SOFFT_ENOMEM / SOFFT_EHIP. */
 sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out);
 
@@ -368,9 +373,21 @@ sofft_status sofft_batch_launch_shape(const sofft_batch* b, int32_t run, int32_t
  * multiples of 16. */
 typedef struct sofft_lp sofft_lp;
 
-/* A network with zero weights (a zero correction).  It owns its weights,
- * Adam moments and activation buffers (grown on demand). */
+/* A network with zero weights (a zero correction).  It owns its parameters,
+ * their gradient and the Adam moments (sofft_lp_param_count() floats each,
+ * allocated here); activations and every other per-call buffer live in a
+ * workspace the caller binds (sofft_lp_workspace_size, sofft_lp_bind). */
 sofft_status sofft_lp_create(sofft_lp** out);
+
+/* Bytes of workspace for calls on `batch` items of ny x nx pixels (forward,
+ * loss, backward, the solver's correction with batch = nE) that may train on
+ * npairs pairs (sofft_lp_train; 0 otherwise).  Host only. */
+sofft_status sofft_lp_workspace_size(int64_t ny, int64_t nx, int32_t batch, int64_t npairs, int64_t* bytes);
+
+/* Bind a caller-owned device workspace (256-byte aligned; NULL unbinds); the
+ * conditions of sofft_plan_bind apply.  Calls needing more than is bound
+ * return SOFFT_EWORKSPACE. */
+sofft_status sofft_lp_bind(sofft_lp* lp, void* workspace, int64_t bytes);
 sofft_status sofft_lp_destroy(sofft_lp* lp);
 int32_t sofft_lp_param_count(void);
 
@@ -390,6 +407,15 @@ sofft_status sofft_lp_forward(sofft_lp* lp, const void* r, const void* pz, int64
  * Blocking. */
 sofft_status sofft_lp_loss_grad(sofft_lp* lp, const void* r, const void* pz, const void* e, int64_t ny,
                                 int64_t nx, int32_t batch, float* grad, double* loss, void* stream);
+
+/* Gradients of the network for gradient checks: a forward pass on (r, pz)
+ * as in sofft_lp_forward, then for the given dL/dN (dout, device FP32
+ * [batch][ny][nx][2]) the input gradient din (device FP32 [batch][ny][nx][4],
+ * with respect to the four packed input channels Re r/s, Im r/s, Re pz/s,
+ * Im pz/s) and the parameter gradient dw (device FP32 [param_count], layout as
+ * above).  Asynchronous. */
+sofft_status sofft_lp_backward(sofft_lp* lp, const void* r, const void* pz, const float* dout, int64_t ny,
+                               int64_t nx, int32_t batch, float* din, float* dw, void* stream);
 
 /* Train on npairs (residual r_k, error e_k = x* - x_k) pairs of the plan's
  * grid, pair k at energy E_host[k] (P^-1 r is formed at that energy):
@@ -419,6 +445,8 @@ typedef enum {
   SOFFT_KERNEL_SSE_ROW_UPD = 5,   /* x, r update, ||r||^2, forward row FFT of r */
   SOFFT_KERNEL_SSE_COL_PREC = 6,  /* column FFT, divide by k^2/2 - E, inverse */
   SOFFT_KERNEL_SSE_ROW_PREC = 7,  /* inverse row FFT to z and r^T z */
+  SOFFT_KERNEL_3D_KINETIC = 8,    /* 3D kinetic pass along one axis (with the potential factors) */
+  SOFFT_KERNEL_3D_STRIP = 9,      /* 3D Crank-Nicolson on the ECS strip of one axis */
   SOFFT_KERNEL_COUNT_ = 16
 } sofft_kernel;
 

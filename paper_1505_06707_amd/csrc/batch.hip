@@ -35,9 +35,9 @@ struct BatchClass {
 };
 
 bool same_problem(const sofft_problem& a, const sofft_problem& b) {
-  return a.ndim == b.ndim && a.dtype == b.dtype && a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.L[0] == b.L[0] &&
-         a.L[1] == b.L[1] && a.R0[0] == b.R0[0] && a.R0[1] == b.R0[1] && a.theta == b.theta &&
-         a.contour == b.contour && a.charge == b.charge && a.a2 == b.a2;
+  return a.ndim == b.ndim && a.dtype == b.dtype && a.n[0] == b.n[0] && a.n[1] == b.n[1] && a.n[2] == b.n[2] &&
+         a.L[0] == b.L[0] && a.L[1] == b.L[1] && a.L[2] == b.L[2] && a.R0[0] == b.R0[0] && a.R0[1] == b.R0[1] &&
+         a.R0[2] == b.R0[2] && a.theta == b.theta && a.contour == b.contour && a.charge == b.charge && a.a2 == b.a2;
 }
 
 }  // namespace

@@ -89,7 +89,7 @@ struct Timing {
 
 struct Plan {
   sofft_problem prob{};
-  Axis ax[2];
+  Axis ax[3];
   std::vector<double> host_partials;
   Timing timing;
   // Caller-owned device workspace (sofft_plan_bind); every buffer of O(grid)
@@ -173,6 +173,11 @@ sofft_status launch_propagate(Plan& p, void* psi, double dt, int64_t nsteps, con
 sofft_status launch_propagate_static(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
                                      hipStream_t s);
 size_t vphase_bytes(const Plan& p);
+// 3D grids (tdse3d.hip).
+sofft_status launch_propagate_3d(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
+                                 const cx<double>* vph, hipStream_t s);
+sofft_status build_octant_vphase(const Plan& p, double dt, cx<double>* table, hipStream_t s);
+sofft_status launch_softcore_3d(const Plan& p, double charge, double a2, void* out, hipStream_t s);
 sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s);
 // V0 = -charge / sqrt(sum z^2 + a2) on the plan's grid into out (complex, [ny][nx]).
 sofft_status launch_softcore(const Plan& p, double charge, double a2, void* out, hipStream_t s);

@@ -193,8 +193,10 @@ __global__ void __launch_bounds__(256) k_lp_loss(const float* y, const cx<double
 }
 
 // dx[q][ci] = (sum over taps and co of W[t][co][ci] dy[q - d_t][co]) * (x[q][ci] > 0),
-// FP32, one thread per pixel; x is the layer's (post-ReLU) input.
-template <int CIN, int COUT>
+// FP32, one thread per pixel; x is the layer's (post-ReLU) input.  MASK =
+// false (the network's input layer, which has no ReLU before it) leaves the
+// gradient unmasked.
+template <int CIN, int COUT, bool MASK = true>
 __global__ void __launch_bounds__(256) k_lp_bwd_data(const float* dy, const float* params, int w_off,
                                                      const _Float16* x, int H, int W, float* dx) {
   __shared__ float w[9 * COUT * CIN];
@@ -221,7 +223,7 @@ __global__ void __launch_bounds__(256) k_lp_bwd_data(const float* dy, const floa
   }
   const size_t o = (size_t(b) * plane + i) * CIN;
 #pragma unroll
-  for (int c = 0; c < CIN; ++c) dx[o + c] = float(x[o + c]) > 0.f ? acc[c] : 0.f;
+  for (int c = 0; c < CIN; ++c) dx[o + c] = (!MASK || float(x[o + c]) > 0.f) ? acc[c] : 0.f;
 }
 
 // Partial weight and bias gradients over a chunk of pixels of every item:
@@ -297,11 +299,62 @@ sofft_status alloc(DevBuf& d, size_t bytes) {
 
 // Network state: master weights, Adam moments and activation buffers.
 struct LpNet {
-  DevBuf params, grad, m, v;
+  DevBuf params, grad, m, v;     // owned: allocated by sofft_lp_create
+  // views into the caller's workspace (sofft_lp_bind), laid out per call
   DevBuf x0, h1, h2, y3, dy3, dh2, dh1, part, loss_part, scale, pz, idx;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
   int64_t adam_t = 0;
   std::vector<double> host_loss;
 };
+
+namespace {
+constexpr int kLpChunks = 256;
+size_t r256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+// Workspace of a call on B items of `plane` pixels that may train on npairs
+// pairs: activations, gradients, partial sums, the pairs' P^-1 r and scales.
+size_t lp_ws_bytes(int B, size_t plane, int64_t npairs) {
+  const size_t pb = (plane + 255) / 256;
+  const size_t n = size_t(B) * plane;
+  return r256(n * 4 * 2) + 2 * r256(n * 16 * 2) + 2 * r256(n * 2 * 4) + 2 * r256(n * 16 * 4) +
+         r256(size_t(kLpChunks) * (9 * 16 * 16 + 16) * 8) + r256(size_t(B) * pb * 8) +
+         r256(size_t(std::max<int64_t>(B, npairs)) * 8) + r256(size_t(npairs) * plane * 16) + r256(size_t(B) * 4);
+}
+
+// Point the per-call buffers into the bound workspace (SOFFT_EWORKSPACE when
+// it is missing or smaller than lp_ws_bytes).
+sofft_status lp_carve(LpNet& net, int B, size_t plane, int64_t npairs) {
+  const size_t need = lp_ws_bytes(B, plane, npairs);
+  if (!net.ws || net.ws_bytes < need) {
+    set_error("the correction network needs a bound workspace of " + std::to_string(need) +
+              " bytes for this call (sofft_lp_workspace_size, sofft_lp_bind); bound: " +
+              std::to_string(net.ws ? net.ws_bytes : 0));
+    return SOFFT_EWORKSPACE;
+  }
+  char* q = static_cast<char*>(net.ws);
+  auto take = [&](DevBuf& d, size_t b) {
+    d.p = q;
+    d.bytes = b;
+    q += r256(b);
+  };
+  const size_t pb = (plane + 255) / 256;
+  const size_t n = size_t(B) * plane;
+  take(net.x0, n * 4 * 2);
+  take(net.h1, n * 16 * 2);
+  take(net.h2, n * 16 * 2);
+  take(net.y3, n * 2 * 4);
+  take(net.dy3, n * 2 * 4);
+  take(net.dh2, n * 16 * 4);
+  take(net.dh1, n * 16 * 4);
+  take(net.part, size_t(kLpChunks) * (9 * 16 * 16 + 16) * 8);
+  take(net.loss_part, size_t(B) * pb * 8);
+  take(net.scale, size_t(std::max<int64_t>(B, npairs)) * 8);
+  take(net.pz, size_t(npairs) * plane * 16);
+  take(net.idx, size_t(B) * 4);
+  return SOFFT_OK;
+}
 
 int lp_param_count() { return kParams; }
 
@@ -345,33 +398,28 @@ sofft_status forward_layers(LpNet& net, int B, int H, int W, const int* active, 
   return SOFFT_OK;
 }
 
+// The buffers of a forward pass (B items) are carved by the entry points.
 sofft_status buffers(LpNet& net, int B, size_t plane) {
-  sofft_status st = alloc(net.x0, size_t(B) * plane * 4 * sizeof(_Float16));
-  if (st == SOFFT_OK) st = alloc(net.h1, size_t(B) * plane * 16 * sizeof(_Float16));
-  if (st == SOFFT_OK) st = alloc(net.h2, size_t(B) * plane * 16 * sizeof(_Float16));
-  return st;
+  if (!net.x0.p || net.x0.bytes < size_t(B) * plane * 4 * 2) {
+    set_error("internal: network buffers not carved");
+    return SOFFT_EUNSUPPORTED;
+  }
+  return SOFFT_OK;
 }
 
 sofft_status train_buffers(LpNet& net, int B, size_t plane, int chunks) {
-  sofft_status st = buffers(net, B, plane);
-  if (st == SOFFT_OK) st = alloc(net.y3, size_t(B) * plane * 2 * sizeof(float));
-  if (st == SOFFT_OK) st = alloc(net.dy3, size_t(B) * plane * 2 * sizeof(float));
-  if (st == SOFFT_OK) st = alloc(net.dh2, size_t(B) * plane * 16 * sizeof(float));
-  if (st == SOFFT_OK) st = alloc(net.dh1, size_t(B) * plane * 16 * sizeof(float));
-  if (st == SOFFT_OK) st = alloc(net.part, size_t(chunks) * (9 * 16 * 16 + 16) * sizeof(double));
-  if (st == SOFFT_OK) st = alloc(net.grad, kParams * sizeof(float));
-  return st;
+  (void)chunks;
+  return buffers(net, B, plane);
 }
 
 // Loss and gradient of one batch (items idx[b] of r, pz, e; scales per pair).
 sofft_status loss_grad(LpNet& net, const cx<double>* r, const cx<double>* pz, const cx<double>* e,
                        const double* scale, const int* idx, int B, int H, int W, hipStream_t s) {
   const size_t plane = size_t(H) * W;
-  constexpr int chunks = 256;
+  constexpr int chunks = kLpChunks;
   sofft_status st = train_buffers(net, B, plane, chunks);
   if (st != SOFFT_OK) return st;
   const unsigned pb = unsigned((plane + 255) / 256);
-  if ((st = alloc(net.loss_part, size_t(B) * pb * sizeof(double))) != SOFFT_OK) return st;
   k_lp_pack<<<dim3(pb, B), 256, 0, s>>>(r, pz, scale, idx, nullptr, plane, static_cast<_Float16*>(net.x0.p));
   SOFFT_HIP_TRY(hipGetLastError());
   if ((st = forward_layers(net, B, H, W, nullptr, kOutF32, nullptr, nullptr, s)) != SOFFT_OK) return st;
@@ -399,6 +447,37 @@ sofft_status loss_grad(LpNet& net, const cx<double>* r, const cx<double>* pz, co
   k_lp_bwd_w<4, 16><<<chunks, 256, 0, s>>>(static_cast<const float*>(net.dh1.p),
                                            static_cast<const _Float16*>(net.x0.p), H, W, B, chunks, part);
   k_lp_reduce<<<(9 * 16 * 4 + 16 + 255) / 256, 256, 0, s>>>(part, chunks, 9 * 16 * 4, 16, kOffW1, kOffB1, G);
+  SOFFT_HIP_TRY(hipGetLastError());
+  return SOFFT_OK;
+}
+
+// Gradients of the network for a given dL/dy of its output (dy3, FP32
+// [B][H][W][2]) after a forward pass that left x0, h1, h2: weights and biases
+// into net.grad, and dL/dx0 (FP32 [B][H][W][4], unmasked) into dx0.
+sofft_status backward_from(LpNet& net, const float* dy3, int B, int H, int W, float* dx0, hipStream_t s) {
+  const size_t plane = size_t(H) * W;
+  constexpr int chunks = kLpChunks;
+  sofft_status st = train_buffers(net, B, plane, chunks);
+  if (st != SOFFT_OK) return st;
+  const unsigned pb = unsigned((plane + 255) / 256);
+  const float* P = static_cast<const float*>(net.params.p);
+  float* G = static_cast<float*>(net.grad.p);
+  double* part = static_cast<double*>(net.part.p);
+  k_lp_bwd_w<16, 2><<<chunks, 256, 0, s>>>(dy3, static_cast<const _Float16*>(net.h2.p), H, W, B, chunks, part);
+  k_lp_reduce<<<(9 * 2 * 16 + 2 + 255) / 256, 256, 0, s>>>(part, chunks, 9 * 2 * 16, 2, kOffW3, kOffB3, G);
+  k_lp_bwd_data<16, 2><<<dim3(pb, B), 256, 0, s>>>(dy3, P, kOffW3, static_cast<const _Float16*>(net.h2.p), H, W,
+                                                   static_cast<float*>(net.dh2.p));
+  k_lp_bwd_w<16, 16><<<chunks, 256, 0, s>>>(static_cast<const float*>(net.dh2.p),
+                                            static_cast<const _Float16*>(net.h1.p), H, W, B, chunks, part);
+  k_lp_reduce<<<(9 * 16 * 16 + 16 + 255) / 256, 256, 0, s>>>(part, chunks, 9 * 16 * 16, 16, kOffW2, kOffB2, G);
+  k_lp_bwd_data<16, 16><<<dim3(pb, B), 256, 0, s>>>(static_cast<const float*>(net.dh2.p), P, kOffW2,
+                                                    static_cast<const _Float16*>(net.h1.p), H, W,
+                                                    static_cast<float*>(net.dh1.p));
+  k_lp_bwd_w<4, 16><<<chunks, 256, 0, s>>>(static_cast<const float*>(net.dh1.p),
+                                           static_cast<const _Float16*>(net.x0.p), H, W, B, chunks, part);
+  k_lp_reduce<<<(9 * 16 * 4 + 16 + 255) / 256, 256, 0, s>>>(part, chunks, 9 * 16 * 4, 16, kOffW1, kOffB1, G);
+  k_lp_bwd_data<4, 16, false><<<dim3(pb, B), 256, 0, s>>>(static_cast<const float*>(net.dh1.p), P, kOffW1,
+                                                          static_cast<const _Float16*>(net.x0.p), H, W, dx0);
   SOFFT_HIP_TRY(hipGetLastError());
   return SOFFT_OK;
 }
@@ -453,6 +532,7 @@ sofft_status sofft_lp_create(sofft_lp** out) {
   sofft_status st = alloc(lp->params, kParams * sizeof(float));
   if (st == SOFFT_OK) st = alloc(lp->m, kParams * sizeof(float));
   if (st == SOFFT_OK) st = alloc(lp->v, kParams * sizeof(float));
+  if (st == SOFFT_OK) st = alloc(lp->grad, kParams * sizeof(float));
   if (st == SOFFT_OK && (hipMemset(lp->params.p, 0, kParams * sizeof(float)) != hipSuccess ||
                          hipMemset(lp->m.p, 0, kParams * sizeof(float)) != hipSuccess ||
                          hipMemset(lp->v.p, 0, kParams * sizeof(float)) != hipSuccess)) {
@@ -460,7 +540,7 @@ sofft_status sofft_lp_create(sofft_lp** out) {
     st = SOFFT_EHIP;
   }
   if (st != SOFFT_OK) {
-    for (DevBuf* b : {&lp->params, &lp->m, &lp->v}) dev_free(*b);
+    for (DevBuf* b : {&lp->params, &lp->m, &lp->v, &lp->grad}) dev_free(*b);
     delete lp;
     return st;
   }
@@ -470,9 +550,7 @@ sofft_status sofft_lp_create(sofft_lp** out) {
 
 sofft_status sofft_lp_destroy(sofft_lp* lp) {
   if (!lp) return SOFFT_OK;
-  for (DevBuf* b : {&lp->params, &lp->grad, &lp->m, &lp->v, &lp->x0, &lp->h1, &lp->h2, &lp->y3, &lp->dy3,
-                    &lp->dh2, &lp->dh1, &lp->part, &lp->loss_part, &lp->scale, &lp->pz, &lp->idx})
-    dev_free(*b);
+  for (DevBuf* b : {&lp->params, &lp->grad, &lp->m, &lp->v}) dev_free(*b);
   delete lp;
   return SOFFT_OK;
 }
@@ -508,9 +586,7 @@ sofft_status sofft_lp_forward(sofft_lp* lp, const void* r, const void* pz, int64
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t plane = size_t(ny) * size_t(nx);
-  sofft_status st = buffers(*lp, batch, plane);
-  if (st == SOFFT_OK) st = alloc(lp->scale, size_t(batch) * sizeof(double));
-  if (st == SOFFT_OK) st = alloc(lp->y3, size_t(batch) * plane * 2 * sizeof(float));
+  sofft_status st = lp_carve(*lp, batch, plane, 0);
   if (st != SOFFT_OK) return st;
   double* scale = static_cast<double*>(lp->scale.p);
   const cx<double>* rv = static_cast<const cx<double>*>(r);
@@ -532,7 +608,7 @@ sofft_status sofft_lp_loss_grad(sofft_lp* lp, const void* r, const void* pz, con
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t plane = size_t(ny) * size_t(nx);
-  sofft_status st = alloc(lp->scale, size_t(batch) * sizeof(double));
+  sofft_status st = lp_carve(*lp, batch, plane, 0);
   if (st != SOFFT_OK) return st;
   double* scale = static_cast<double*>(lp->scale.p);
   const cx<double>* rv = static_cast<const cx<double>*>(r);
@@ -542,6 +618,33 @@ sofft_status sofft_lp_loss_grad(sofft_lp* lp, const void* r, const void* pz, con
     return st;
   SOFFT_HIP_TRY(hipMemcpyAsync(grad, lp->grad.p, kParams * sizeof(float), hipMemcpyDeviceToDevice, s));
   return read_loss(*lp, batch, plane, loss, s);
+}
+
+sofft_status sofft_lp_backward(sofft_lp* lp, const void* r, const void* pz, const float* dout, int64_t ny,
+                               int64_t nx, int32_t batch, float* din, float* dw, void* stream) {
+  if (!lp || !r || !pz || !dout || !din || !dw || ny <= 0 || nx <= 0 || batch <= 0) {
+    set_error("bad argument to sofft_lp_backward");
+    return SOFFT_EINVAL;
+  }
+  if (nx % 16 != 0) {
+    set_error("the correction network needs grid widths that are multiples of 16");
+    return SOFFT_EUNSUPPORTED;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t plane = size_t(ny) * size_t(nx);
+  sofft_status st = lp_carve(*lp, batch, plane, 0);
+  if (st != SOFFT_OK) return st;
+  double* scale = static_cast<double*>(lp->scale.p);
+  const cx<double>* rv = static_cast<const cx<double>*>(r);
+  if ((st = lp_rms(rv, batch, plane, scale, s)) != SOFFT_OK) return st;
+  k_lp_pack<<<dim3(unsigned((plane + 255) / 256), batch), 256, 0, s>>>(
+      rv, static_cast<const cx<double>*>(pz), scale, nullptr, nullptr, plane, static_cast<_Float16*>(lp->x0.p));
+  SOFFT_HIP_TRY(hipGetLastError());
+  if ((st = forward_layers(*lp, batch, int(ny), int(nx), nullptr, kOutF32, nullptr, nullptr, s)) != SOFFT_OK)
+    return st;
+  if ((st = backward_from(*lp, dout, batch, int(ny), int(nx), din, s)) != SOFFT_OK) return st;
+  SOFFT_HIP_TRY(hipMemcpyAsync(dw, lp->grad.p, kParams * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return SOFFT_OK;
 }
 
 sofft_status sofft_lp_train(sofft_lp* lp, sofft_plan* plan, const void* r, const void* e, const double* E_host,
@@ -561,9 +664,7 @@ sofft_status sofft_lp_train(sofft_lp* lp, sofft_plan* plan, const void* r, const
   const size_t plane = size_t(H) * W;
   const cx<double>* rv = static_cast<const cx<double>*>(r);
   const cx<double>* ev = static_cast<const cx<double>*>(e);
-  sofft_status st = alloc(lp->pz, size_t(npairs) * plane * sizeof(cx<double>));
-  if (st == SOFFT_OK) st = alloc(lp->scale, size_t(npairs) * sizeof(double));
-  if (st == SOFFT_OK) st = alloc(lp->idx, size_t(batch) * sizeof(int));
+  sofft_status st = lp_carve(*lp, batch, plane, npairs);
   if (st != SOFFT_OK) return st;
   cx<double>* pz = static_cast<cx<double>*>(lp->pz.p);
   // P^-1 r of every pair at its energy, and the scales
@@ -628,8 +729,31 @@ sofft_status sofft_sse_solve_learned(sofft_plan* plan, sofft_lp* lp, const void*
     set_error("the correction network needs grid widths that are multiples of 16");
     return SOFFT_EUNSUPPORTED;
   }
+  if (p.prob.ndim == 2) {
+    const sofft_status st = lp_carve(*lp, nE, size_t(p.ax[0].n) * size_t(p.ax[1].n), 0);
+    if (st != SOFFT_OK) return st;
+  }
   return sse_solve(p, f, f_per_energy, E_host, nE, field, x_out, rtol, maxit, stats,
                    reinterpret_cast<hipStream_t>(stream), lp, patience);
+}
+
+sofft_status sofft_lp_workspace_size(int64_t ny, int64_t nx, int32_t batch, int64_t npairs, int64_t* bytes) {
+  if (ny <= 0 || nx <= 0 || batch <= 0 || npairs < 0 || !bytes) {
+    set_error("bad argument to sofft_lp_workspace_size");
+    return SOFFT_EINVAL;
+  }
+  *bytes = int64_t(lp_ws_bytes(batch, size_t(ny) * size_t(nx), npairs));
+  return SOFFT_OK;
+}
+
+sofft_status sofft_lp_bind(sofft_lp* lp, void* workspace, int64_t bytes) {
+  if (!lp || bytes < 0 || (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)) {
+    set_error("bad argument to sofft_lp_bind (the workspace must be 256-byte aligned)");
+    return SOFFT_EINVAL;
+  }
+  lp->ws = workspace;
+  lp->ws_bytes = workspace ? size_t(bytes) : 0;
+  return SOFFT_OK;
 }
 
 }  // extern "C"

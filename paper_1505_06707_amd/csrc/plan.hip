@@ -57,7 +57,8 @@ static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
 WsLayout plan_ws_layout(const Plan& p, int n_energies) {
   WsLayout L;
-  const size_t npts = size_t(p.ax[0].n) * (p.prob.ndim == 2 ? size_t(p.ax[1].n) : 1);
+  size_t npts = 1;
+  for (int d = 0; d < p.prob.ndim; ++d) npts *= size_t(p.ax[d].n);
   L.vphase = 0;
   L.partials = round256(npts * sizeof(cx<double>));
   L.solver = L.partials + round256(kNormBlocks * sizeof(double));
@@ -459,8 +460,8 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
   }
   *out = nullptr;
   const sofft_problem& p = *prob;
-  if (p.ndim != 1 && p.ndim != 2) {
-    set_error("ndim must be 1 or 2");
+  if (p.ndim < 1 || p.ndim > 3) {
+    set_error("ndim must be 1, 2 or 3");
     return SOFFT_EINVAL;
   }
   if (p.dtype != SOFFT_C128 && p.dtype != SOFFT_C64) {
@@ -485,7 +486,8 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
     return SOFFT_EINVAL;
   }
   for (int d = 0; d < p.ndim; ++d) {
-    if (!supported_length(p.n[d]) || (p.ndim == 2 && p.n[d] > 1024)) {
+    const bool pow2 = p.n[d] > 0 && (p.n[d] & (p.n[d] - 1)) == 0;
+    if (!supported_length(p.n[d]) || (p.ndim == 2 && p.n[d] > 1024) || (p.ndim == 3 && (p.n[d] > 512 || !pow2))) {
       set_error("unsupported grid length " + std::to_string(p.n[d]));
       return SOFFT_EUNSUPPORTED;
     }
@@ -504,13 +506,18 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
   // lane: at most 256 strip nodes per axis.
   for (int d = 0; d < p.ndim; ++d) {
     sofft_status st = build_axis(pl->ax[d], p.n[d], p.L[d], p.R0[d], p.theta, p.contour);
-    if (st == SOFFT_OK && p.ndim == 2 && pl->ax[d].m > 256) {
-      set_error("ECS strip of " + std::to_string(pl->ax[d].m) + " nodes exceeds 256 per axis in 2D; increase R0");
+    if (st == SOFFT_OK && p.ndim >= 2 && pl->ax[d].m > 256) {
+      set_error("ECS strip of " + std::to_string(pl->ax[d].m) + " nodes exceeds 256 per axis in 2D and 3D; "
+                "increase R0");
+      st = SOFFT_EUNSUPPORTED;
+    }
+    if (st == SOFFT_OK && pl->ax[d].m > pl->ax[d].n / 2) {
+      set_error("ECS strip of " + std::to_string(pl->ax[d].m) + " nodes exceeds half the axis; increase R0");
       st = SOFFT_EUNSUPPORTED;
     }
     if (st == SOFFT_OK) st = upload_static(pl->ax[d], p.ndim == 2 && p.dtype == SOFFT_C128);
     if (st != SOFFT_OK) {
-      for (int e = 0; e < 2; ++e) free_axis(pl->ax[e]);
+      for (int e = 0; e < 3; ++e) free_axis(pl->ax[e]);
       delete pl;
       return st;
     }
@@ -521,7 +528,7 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
 
 sofft_status sofft_plan_destroy(sofft_plan* plan) {
   if (!plan) return SOFFT_OK;
-  for (int d = 0; d < 2; ++d) free_axis(plan->ax[d]);
+  for (int d = 0; d < 3; ++d) free_axis(plan->ax[d]);
   delete plan;
   return SOFFT_OK;
 }

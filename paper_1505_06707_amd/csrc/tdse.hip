@@ -13,55 +13,11 @@
 #include <vector>
 
 #include "line_fft.hpp"
+#include "passes.hpp"
 #include "potential.hpp"
 #include "internal.hpp"
 
 namespace sofft {
-
-// A complex128 or complex64 state (T = double or float) is loaded from HBM,
-// transformed and propagated in FP64 registers with FP64 tables, and rounded
-// to T only when stored.  Line exchanges and the CN reduction go through LDS
-// in FP64 (xch_t): an FP32 exchange for complex64 measured 3% faster and 3x
-// the error.
-template <typename T>
-using xch_t = double;
-
-template <typename T>
-struct PassArgs {
-  cx<T>* psi;              // the state (one run), or
-  cx<T>* const* runs;      // device array of nruns states of the same shape
-  const double* const* f_runs;   // device array of their f_mid rows (may be null)
-  int nruns;               // runs of this shape (lines of a pass: nruns * ny or nruns * nx)
-  int ntiles;              // blocks of lines over all runs
-  const int64_t* step_base;      // device offset added to step (graph replays), or null
-  int nx, ny;
-  const cx<double>* tw;    // twiddles exp(-2 pi i u/n) of the pass axis
-  const cx<double>* kin;   // kinetic phase (with 1/n) of the pass axis
-  int do_pot;         // apply the potential half-step and the CN sweep
-  const double* f_mid;     // f_mid of the single state
-  int64_t step;
-  double ht;          // dt/2
-  double charge, a2;
-  const double* x;        // x nodes
-  const cx<double>* zx;   // z(x_j)
-  const cx<double>* zy;   // z(y_j) (2D) or null
-  const cx<double>* vph;  // exp(-i V0(z) dt/2) on the quadrant j < n/2 of each axis, [ny/2][nx/2]
-                          // (1D: [nx/2]); node j reads entry vfold(j, n); null when V0 = 0
-  int vfull;              // vph holds the whole grid, [ny][nx] (a caller's V0, no symmetry)
-  const double* w;        // W of the field term f W on the grid, [ny][nx]; null: W = x
-  int j0, m, levels;      // ECS strip of the pass axis
-  int j0y, my;            // ECS strip of the y axis (row pass of a 2D grid)
-  const cx<double>* alpha;
-  const cx<double>* gamma;
-  const cx<double>* binv;
-  int lds_line;           // LDS elements (of xch_t<T>) reserved per line
-};
-
-// The static potential is even in x and in y on every contour (z(-x) = -z(x)
-// enters V0 through z^2), so its phase table keeps one quadrant: node j of an
-// axis of n nodes reads entry min(j, n - 1 - j), the mirror node on the
-// negative side.
-__host__ __device__ __forceinline__ int vfold(int j, int n) { return j < n - 1 - j ? j : n - 1 - j; }
 
 // Crank-Nicolson on the ECS strip of a line held by the whole block (1D):
 // y = 2 B^-1 v - v by parallel cyclic reduction, staged in the line's LDS
@@ -187,75 +143,6 @@ constexpr int fft_buffers() {
   return (N <= 1024 && bytes <= 128 * 1024) ? 2 : 1;
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Crank-Nicolson solve B u = v on one line's strip by parallel cyclic
-// reduction with the coefficients the host prepared (truncated once the
-// couplings fall below FP64 rounding).  The host zeroes alpha where p - 2^l <
-// 0 and gamma where p + 2^l >= m, so neighbours are read at clamped indices
-// without branches; the next level's coefficients are fetched while the
-// current level is reduced.  Levels ping-pong between [0, m) and [m, 2m); on
-// entry [0, m) holds v, on exit u is in the buffer cn_result(m, levels).
-//
-// The positions of a line are split into groups of 64 (one per lane of a
-// wavefront); k wavefronts share the line, wavefront q taking groups q, q + k,
-// ... (the host keeps 2D strips at m <= 256, so at most 4 groups).  With k > 1
-// the levels are separated by block barriers, with k = 1 by wavefront ones.
-constexpr int kPcrGroups = 4;
-__host__ __device__ __forceinline__ int cn_result(int m, int levels) { return (levels & 1) ? 0 : m; }
-
-template <typename T, int N, typename X>
-__device__ __forceinline__ void pcr_line(const LineLDS<X>& Lw, int lane, int q, int k, const PassArgs<T>& a) {
-  constexpr int W = N / 128 > 0 ? (N / 128 < kPcrGroups ? N / 128 : kPcrGroups) : 1;
-  const int m = a.m, levels = a.levels;
-  const int ngroups = (m + 63) >> 6;
-  int src = 0, dst = m;
-  cx<double> al[W], ga[W];
-#pragma unroll
-  for (int i = 0; i < W; ++i) {
-    const int p = min(lane + 64 * (q + k * i), m - 1);
-    if (levels > 0 && q + k * i < ngroups) {
-      al[i] = a.alpha[p];
-      ga[i] = a.gamma[p];
-    }
-  }
-  for (int l = 0; l < levels; ++l) {
-    const int st = 1 << l;
-    const cx<double>* aln = a.alpha + size_t(l + 1 < levels ? l + 1 : l) * m;
-    const cx<double>* gan = a.gamma + size_t(l + 1 < levels ? l + 1 : l) * m;
-#pragma unroll
-    for (int i = 0; i < W; ++i) {
-      if (q + k * i < ngroups) {   // uniform over the wavefront
-        const int p0 = lane + 64 * (q + k * i), p = min(p0, m - 1);
-        const cx<double> d = widen(Lw[src + p]) - cmul(al[i], widen(Lw[src + max(p - st, 0)])) -
-                             cmul(ga[i], widen(Lw[src + min(p + st, m - 1)]));
-        al[i] = aln[p];
-        ga[i] = gan[p];
-        if (p0 < m) Lw[dst + p] = narrow<X>(d);
-      }
-    }
-    if (k > 1)
-      __syncthreads();
-    else
-      wave_sync();
-    const int tmp = src;
-    src = dst;
-    dst = tmp;
-  }
-#pragma unroll
-  for (int i = 0; i < W; ++i) {
-    if (q + k * i < ngroups) {
-      const int p0 = lane + 64 * (q + k * i), p = min(p0, m - 1);
-      const cx<double> u = cmul(a.binv[p], widen(Lw[src + p]));
-      if (p0 < m) Lw[dst + p] = narrow<X>(u);
-    }
-  }
-}
-
 // All lines of the block; line_of(ln) gives the LDS view of line ln.  With at
 // least as many wavefronts as lines (and a multiple of them) every wavefront
 // works on one line, k = nwaves / lines sharing it; otherwise wavefront w
@@ -271,25 +158,6 @@ __device__ __forceinline__ void cn_block(int lpb, const PassArgs<T>& a, LineOf l
     for (int ln = w; ln < lpb; ln += nw) pcr_line<T, N>(line_of(ln), lane, 0, 1, a);
   }
   __syncthreads();
-}
-
-// One element of a state through a global-address-space pointer: the state
-// pointer comes from a select (one state, or the batch's pointer table), so
-// the compiler cannot prove it global and would emit flat accesses, which
-// also count against the LDS counter that the pass's barriers wait on.
-template <typename T>
-__device__ __forceinline__ cx<T> gload(const cx<T>* p) {
-  using V = T __attribute__((ext_vector_type(2)));
-  const V v = *(const __attribute__((address_space(1))) V*)(p);
-  return {v.x, v.y};
-}
-template <typename T>
-__device__ __forceinline__ void gstore(cx<T>* p, cx<T> c) {
-  using V = T __attribute__((ext_vector_type(2)));
-  V v;
-  v.x = c.re;
-  v.y = c.im;
-  *(__attribute__((address_space(1))) V*)(p) = v;
 }
 
 template <typename T>
@@ -931,12 +799,24 @@ static sofft_status occupancy_n(bool row, int n, int lds_line, int threads, int*
 // whole grid for a caller's V0; 0 when the plan has no potential.
 size_t vphase_bytes(const Plan& p) {
   if (p.prob.charge == 0.0 && !p.user_v0) return 0;
-  const size_t nx = size_t(p.ax[0].n), ny = p.prob.ndim == 2 ? size_t(p.ax[1].n) : 1;
-  return (p.user_v0 ? nx * ny : (nx / 2) * (p.prob.ndim == 2 ? ny / 2 : 1)) * sizeof(cx<double>);
+  size_t full = 1, fold = 1;
+  for (int d = 0; d < p.prob.ndim; ++d) {
+    full *= size_t(p.ax[d].n);
+    fold *= size_t(p.ax[d].n) / 2;
+  }
+  return (p.user_v0 ? full : fold) * sizeof(cx<double>);
 }
 
 // Write the table of exp(-i V0 dt/2) of the plan into `table` (vphase_bytes).
 static sofft_status build_vphase(const Plan& p, double dt, cx<double>* table, hipStream_t s) {
+  if (p.prob.ndim == 3 && !p.user_v0) return build_octant_vphase(p, dt, table, s);
+  if (p.prob.ndim == 3) {
+    const size_t n = size_t(p.ax[0].n) * p.ax[1].n * p.ax[2].n;
+    k_vphase_user<<<unsigned((n + 255) / 256), 256, 0, s>>>(table, static_cast<const cx<double>*>(p.user_v0), n,
+                                                          0.5 * dt);
+    SOFFT_HIP_TRY(hipGetLastError());
+    return SOFFT_OK;
+  }
   const bool full = p.user_v0 != nullptr;
   const int ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
   const int hx = int(p.ax[0].n) / 2, hy = p.prob.ndim == 2 ? ny / 2 : 1;
@@ -1079,6 +959,7 @@ static sofft_status propagate_1d(Plan& p, void* psi, double dt, int64_t nsteps, 
 static sofft_status propagate_with(Plan& p, void* psi, double dt, int64_t nsteps, const double* f_mid,
                                    const cx<double>* vph, hipStream_t s) {
   const bool c128 = p.prob.dtype == SOFFT_C128;
+  if (p.prob.ndim == 3) return launch_propagate_3d(p, psi, dt, nsteps, f_mid, vph, s);
   if (p.prob.ndim == 1)
     return c128 ? propagate_1d<double>(p, psi, dt, nsteps, f_mid, vph, s)
                 : propagate_1d<float>(p, psi, dt, nsteps, f_mid, vph, s);
@@ -1149,7 +1030,8 @@ sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s) 
   WsLayout L;
   sofft_status st = plan_ws_check(p, 0, &L);
   if (st != SOFFT_OK) return st;
-  int64_t n = p.ax[0].n * (p.prob.ndim == 2 ? p.ax[1].n : 1);
+  int64_t n = 1;
+  for (int d = 0; d < p.prob.ndim; ++d) n *= p.ax[d].n;
   const int blocks = int(std::min<int64_t>(kNormBlocks, (n + 255) / 256));
   double* part = reinterpret_cast<double*>(ws_at(p, L.partials));
   if (p.prob.dtype == SOFFT_C128)
@@ -1167,6 +1049,7 @@ sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s) 
 }
 
 sofft_status launch_softcore(const Plan& p, double charge, double a2, void* out, hipStream_t s) {
+  if (p.prob.ndim == 3) return launch_softcore_3d(p, charge, a2, out, s);
   const int nx = int(p.ax[0].n), ny = p.prob.ndim == 2 ? int(p.ax[1].n) : 1;
   const size_t n = size_t(nx) * ny;
   k_softcore<<<unsigned((n + 255) / 256), 256, 0, s>>>(

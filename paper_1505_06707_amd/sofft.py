@@ -40,9 +40,9 @@ class Problem(ctypes.Structure):
     _fields_ = [
         ("ndim", ctypes.c_int32),
         ("dtype", ctypes.c_int32),
-        ("n", ctypes.c_int64 * 2),
-        ("L", ctypes.c_double * 2),
-        ("R0", ctypes.c_double * 2),
+        ("n", ctypes.c_int64 * 3),
+        ("L", ctypes.c_double * 3),
+        ("R0", ctypes.c_double * 3),
         ("theta", ctypes.c_double),
         ("contour", ctypes.c_int32),
         ("charge", ctypes.c_double),
@@ -105,6 +105,9 @@ _SIGS = {
     "sofft_lp_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p)]),
     "sofft_lp_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sofft_lp_param_count": (ctypes.c_int32, []),
+    "sofft_lp_workspace_size": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                               ctypes.POINTER(ctypes.c_int64)]),
+    "sofft_lp_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "sofft_lp_set_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_lp_get_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_lp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -112,6 +115,9 @@ _SIGS = {
     "sofft_lp_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "sofft_lp_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_lp_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]),
@@ -126,6 +132,7 @@ _SIGS = {
 
 KERNEL_ROW, KERNEL_COL, KERNEL_1D = 0, 1, 2
 KERNEL_SSE_ROW_MV, KERNEL_SSE_COL_MV, KERNEL_SSE_ROW_UPD, KERNEL_SSE_COL_PREC, KERNEL_SSE_ROW_PREC = 3, 4, 5, 6, 7
+KERNEL_3D_KINETIC, KERNEL_3D_STRIP = 8, 9
 
 
 def exported_symbols():
@@ -384,6 +391,7 @@ class Plan:
         E = np.ascontiguousarray(np.asarray(energies, dtype=np.float64).ravel())
         nE = len(E)
         self.ensure_workspace(nE)
+        lp.ensure_workspace(self.shape[0], self.shape[1], nE)
         per = 1 if f.numel() == nE * self.numel and nE > 1 else 0
         fptr = _dev_ptr(f, torch.complex128, self.numel * (nE if per else 1), "f")
         if out is None:
@@ -518,11 +526,30 @@ class LearnedCorrection:
         _check(lib().sofft_lp_create(ctypes.byref(h)))
         self._h = h
         self.nparams = int(lib().sofft_lp_param_count())
+        self._ws = None
+        self._ws_bytes = 0
+
+    def ensure_workspace(self, ny, nx, batch, npairs=0):
+        """Allocate (with torch) and bind a workspace for calls on `batch`
+        items of ny x nx that may train on npairs pairs, if the bound one is
+        smaller."""
+        b = ctypes.c_int64()
+        _check(lib().sofft_lp_workspace_size(int(ny), int(nx), int(batch), int(npairs), ctypes.byref(b)))
+        if b.value <= self._ws_bytes:
+            return
+        if self._ws is not None:
+            import torch
+            torch.cuda.current_stream().synchronize()
+            _check(lib().sofft_lp_bind(self._h, ctypes.c_void_p(0), 0))
+        self._ws, ptr = device_workspace(b.value)
+        _check(lib().sofft_lp_bind(self._h, ctypes.c_void_p(ptr), b.value))
+        self._ws_bytes = b.value
 
     def close(self):
         if getattr(self, "_h", None):
             lib().sofft_lp_destroy(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -545,6 +572,7 @@ class LearnedCorrection:
         """N's output [B][ny][nx][2] (float32 device tensor) for complex128 r, pz [B][ny][nx]."""
         import torch
         B, ny, nx = r.shape
+        self.ensure_workspace(ny, nx, B)
         out = torch.empty((B, ny, nx, 2), dtype=torch.float32, device=r.device)
         _check(lib().sofft_lp_forward(self._h, _dev_ptr(r, torch.complex128, r.numel(), "r"),
                                       _dev_ptr(pz, torch.complex128, r.numel(), "pz"), ny, nx, B,
@@ -555,6 +583,7 @@ class LearnedCorrection:
         """(loss, gradient as a numpy float32 vector) of one batch."""
         import torch
         B, ny, nx = r.shape
+        self.ensure_workspace(ny, nx, B)
         g = torch.empty(self.nparams, dtype=torch.float32, device=r.device)
         loss = ctypes.c_double()
         _check(lib().sofft_lp_loss_grad(self._h, _dev_ptr(r, torch.complex128, r.numel(), "r"),
@@ -563,6 +592,21 @@ class LearnedCorrection:
                                         _dev_ptr(g, torch.float32, g.numel(), "grad"), ctypes.byref(loss),
                                         _stream(stream)))
         return loss.value, g.cpu().numpy()
+
+    def backward(self, r, pz, dout, stream=None):
+        """(din [B][ny][nx][4], dw [param_count]) float32 device tensors for
+        dL/dN = dout [B][ny][nx][2] at inputs r, pz [B][ny][nx] (complex128)."""
+        import torch
+        B, ny, nx = r.shape
+        self.ensure_workspace(ny, nx, B)
+        din = torch.empty((B, ny, nx, 4), dtype=torch.float32, device=r.device)
+        dw = torch.empty(self.nparams, dtype=torch.float32, device=r.device)
+        _check(lib().sofft_lp_backward(self._h, _dev_ptr(r, torch.complex128, r.numel(), "r"),
+                                       _dev_ptr(pz, torch.complex128, r.numel(), "pz"),
+                                       _dev_ptr(dout, torch.float32, B * ny * nx * 2, "dout"), ny, nx, B,
+                                       _dev_ptr(din, torch.float32, din.numel(), "din"),
+                                       _dev_ptr(dw, torch.float32, dw.numel(), "dw"), _stream(stream)))
+        return din, dw
 
     def train(self, plan, r, e, energies, epochs, batch, lr=1e-3, seed=0, stream=None):
         """Train on (r_k, e_k) pairs [npairs][ny][nx] of the plan's grid; returns the per-epoch losses."""
@@ -573,6 +617,7 @@ class LearnedCorrection:
             raise ValueError("one energy per pair is needed")
         losses = np.zeros(epochs, dtype=np.float64)
         plan.ensure_workspace(1)
+        self.ensure_workspace(r.shape[1], r.shape[2], int(batch), n)
         _check(lib().sofft_lp_train(self._h, plan._h, _dev_ptr(r, torch.complex128, r.numel(), "r"),
                                     _dev_ptr(e, torch.complex128, r.numel(), "e"),
                                     E.ctypes.data_as(ctypes.c_void_p), n, int(epochs), int(batch), float(lr),

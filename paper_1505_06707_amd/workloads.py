@@ -23,6 +23,10 @@ Workloads (all atomic units):
   1000 steps each.
 * ``learned_2d`` -- stationary equation on 1024 x 1024 at 64 energies in
   [0.05, 2.0] with the ``sse_2d`` source recipe.
+* ``tdse_3d``  -- 3D TDSE on 256^3, h = 0.4 (box +-51.2), soft-core
+  -1/sqrt(x^2 + y^2 + z^2 + 0.64), the same pulse along x, SECS on all six
+  faces from 80% of the half-width, end angle 0.5; Gaussian with a seeded
+  centre in [-2, 2]^3 and momentum in [-0.5, 0.5]^3; dt = 0.05.
 """
 from dataclasses import dataclass, field
 
@@ -110,7 +114,29 @@ class SSE2D:
         return np.linspace(self.E_lo, self.E_hi, self.n_energies)
 
 
+@dataclass(frozen=True)
+class TDSE3D:
+    n: int = 256
+    h: float = 0.4
+    theta: float = 0.5
+    charge: float = 1.0
+    a2: float = 0.64
+    pulse: Pulse = field(default_factory=Pulse)
+    dt: float = 0.05
+    nsteps: int = 100
+    R0_frac: float = 0.8
+
+    @property
+    def L(self):
+        return self.n * self.h
+
+    @property
+    def R0(self):
+        return self.R0_frac * self.L / 2
+
+
 TDSE_1D = TDSE1D()
+TDSE_3D = TDSE3D()
 TDSE_2D = TDSE2D()
 SSE_2D = SSE2D()
 LEARNED_2D = SSE2D(n=1024, n_energies=64)
@@ -168,3 +194,21 @@ def batch_runs(seed, nruns=96, sizes=BATCH_SIZES):
         omega = float(rng.uniform(0.04, 0.08))
         runs.append(dict(n=n, pulse=Pulse(E0=E0, omega=omega), packet_seed=int(rng.integers(1 << 30))))
     return runs
+
+
+def packet_params_3d(seed):
+    """Seeded centre in [-2, 2]^3 and momentum in [-0.5, 0.5]^3."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-2.0, 2.0, size=3)
+    k = rng.uniform(-0.5, 0.5, size=3)
+    return dict(x0=float(c[0]), y0=float(c[1]), z0=float(c[2]), px=float(k[0]), py=float(k[1]), pz=float(k[2]))
+
+
+def gaussian_3d(x, y, z, x0=0.0, y0=0.0, z0=0.0, px=0.0, py=0.0, pz=0.0):
+    """pi^{-3/4} exp(-|r - r0|^2/2 + i p.r) on the [nz][ny][nx] grid of the
+    1D point sets x (fast), y and z."""
+    X = np.asarray(x, dtype=float)[None, None, :]
+    Y = np.asarray(y, dtype=float)[None, :, None]
+    Z = np.asarray(z, dtype=float)[:, None, None]
+    return (np.pi ** -0.75 * np.exp(-((X - x0) ** 2 + (Y - y0) ** 2 + (Z - z0) ** 2) / 2
+                                    + 1j * (px * X + py * Y + pz * Z)))

@@ -46,7 +46,8 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(ndim=3), -1),
+    (dict(ndim=4), -1),
+    (dict(ndim=0), -1),
     (dict(dtype=7), -1),
     (dict(contour=9), -1),
     (dict(theta=0.0), -1),
@@ -79,3 +80,22 @@ def test_workspace_calls_reject_null_arguments():
     assert L.sofft_plan_bind(None, None, 0) == -1
     assert L.sofft_batch_workspace_size(None, ctypes.byref(n)) == -1
     assert L.sofft_batch_bind(None, None, 0) == -1
+
+
+def _create3(n):
+    p = sofft.Problem()
+    p.ndim, p.dtype = 3, sofft.C128
+    for d in range(3):
+        p.n[d] = n[d]
+        p.L[d] = 0.2 * n[d]
+        p.R0[d] = 0.08 * n[d]
+    p.theta, p.contour, p.charge, p.a2 = 0.5, sofft.SECS, 1.0, 0.64
+    h = ctypes.c_void_p()
+    return sofft.lib().sofft_plan_create(ctypes.byref(p), ctypes.byref(h))
+
+
+@pytest.mark.parametrize("n", [(1024, 16, 16), (96, 64, 64), (64, 48, 64), (64, 64, 0)])
+def test_3d_plan_validation(n):
+    """3D lines are powers of two from 16 to 512: other lengths are rejected
+    before any device work."""
+    assert _create3(n) == -2

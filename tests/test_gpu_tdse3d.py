@@ -1,0 +1,174 @@
+"""GPU parity of the 3D propagation (the separable reading of the Sec. II
+step on three axes) against the FP64 oracle, element by element, with
+packets driven into the ECS strips of every axis (the strip passes act on
+data), the soft-core potential on the contour and the pulse along x.
+Tolerance: relative L2 <= 1e-10 in FP64, <= 1e-5 for a complex64 state."""
+import numpy as np
+import pytest
+
+from oracle import tdse as ot
+from paper_1505_06707_amd import workloads as wl
+from tests.helpers import rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-10, 1e-5
+
+
+def _sofft():
+    from paper_1505_06707_amd import sofft
+    return sofft
+
+
+def _axes(nx, ny, nz, h=0.2, frac=0.8):
+    return [ot.Axis(n, n * h, R0=frac * n * h / 2) for n in (nx, ny, nz)]
+
+
+def _outgoing_3d(ax, ay, az, speed=2.5, inset=1.5):
+    """Six packets, each `inset` inside R0 of one axis and moving outward along it."""
+    X, Y, Z = ax.x[None, None, :], ay.x[None, :, None], az.x[:, None, None]
+    psi = np.zeros((az.n, ay.n, ax.n), dtype=complex)
+    for d, (A, R0) in enumerate(((X, ax.R0), (Y, ay.R0), (Z, az.R0))):
+        for sgn in (1, -1):
+            c = [0.0, 0.0, 0.0]
+            c[d] = sgn * (R0 - inset)
+            k = [0.0, 0.0, 0.0]
+            k[d] = sgn * speed
+            psi += np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / 2
+                          + 1j * (k[0] * X + k[1] * Y + k[2] * Z))
+    return psi
+
+
+def run_gpu_3d(axes, psi0, dt, f_mid, dtype, charge=1.0, a2=0.64, static=False):
+    s = _sofft()
+    plan = s.Plan([a.n for a in axes], [a.L for a in axes], R0=[a.R0 for a in axes], theta=0.5,
+                  charge=charge, a2=a2, dtype=dtype)
+    cdt = np.complex128 if dtype == s.C128 else np.complex64
+    psi = torch.from_numpy(psi0.astype(cdt)).cuda()
+    f = torch.from_numpy(np.asarray(f_mid, dtype=np.float64)).cuda() if len(f_mid) else None
+    if static:
+        import ctypes
+        st = s.lib().sofft_propagate_static(plan._h, ctypes.c_void_p(psi.data_ptr()), float(dt), len(f_mid),
+                                            ctypes.c_void_p(f.data_ptr()) if f is not None else None,
+                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == 0
+    else:
+        plan.propagate(psi, dt, len(f_mid), f)
+    torch.cuda.synchronize()
+    out = psi.cpu().numpy().astype(np.complex128)
+    plan.close()
+    return out
+
+
+SHAPES = [(64, 32, 16), (16, 64, 32), (32, 16, 64), (128, 32, 16), (16, 16, 256), (32, 512, 16)]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_3d_parity_with_amplitude_on_the_strips(shape, dtype):
+    s = _sofft()
+    print(f"3D {shape} {dtype}", flush=True)
+    axes = _axes(*shape)
+    psi0 = _outgoing_3d(*axes)
+    f = wl.Pulse(E0=0.08, omega=0.3, cycles=2).at_midpoints(0.0, 0.05, 40)
+    o = ot.Problem3D(*axes, Zc=1.0, a2=0.64).propagate(psi0, 0.05, f)
+    ax, ay, az = axes
+    strip = ((np.abs(ax.x) > ax.R0)[None, None, :] | (np.abs(ay.x) > ay.R0)[None, :, None]
+             | (np.abs(az.x) > az.R0)[:, None, None])
+    assert np.linalg.norm(o[strip]) > 0.05 * np.linalg.norm(o)
+    g = run_gpu_3d(axes, psi0, 0.05, f, s.C128 if dtype == "c128" else s.C64)
+    err = rel_l2(g, o)
+    print(f"   rel L2 = {err:.3e}", flush=True)
+    assert err < (TOL64 if dtype == "c128" else TOL32)
+
+
+def test_3d_free_gaussian_closed_form_on_gpu():
+    from tests import closed_forms as cf
+    s = _sofft()
+    axes = [ot.Axis(n, L, R0=0.4 * L) for n, L in ((128, 51.2), (64, 25.6), (64, 25.6))]
+    ax, ay, az = axes
+    X, Y, Z = ax.x[None, None, :], ay.x[None, :, None], az.x[:, None, None]
+    g0 = cf.free_gaussian(X, 0.0, 0.5, 0.6) * cf.free_gaussian(Y, 0.0, -0.3, -0.4) * cf.free_gaussian(Z, 0.0, 0.2, 0.1)
+    out = run_gpu_3d(axes, g0, 0.05, np.zeros(12), s.C128, charge=0.0)
+    want = cf.free_gaussian(X, 0.6, 0.5, 0.6) * cf.free_gaussian(Y, 0.6, -0.3, -0.4) * cf.free_gaussian(Z, 0.6, 0.2, 0.1)
+    # the 1D spectral truncation of these packets on the same axes is ~1e-11
+    assert rel_l2(out, want) < 5e-11
+
+
+def test_3d_caller_potential():
+    """U = V0 + f W with a caller's V0 (not symmetric under the octant fold) and W."""
+    s = _sofft()
+    axes = _axes(32, 16, 64)
+    ax, ay, az = axes
+    X, Y, Z = ax.x[None, None, :], ay.x[None, :, None], az.x[:, None, None]
+    rng = np.random.default_rng(8)
+    V0 = (-1.0 / np.sqrt((X - 0.4) ** 2 + (Y + 0.2) ** 2 + Z ** 2 + 0.5) + 0.01j * rng.normal(size=(64, 16, 32))
+          ).astype(complex)
+    W = np.broadcast_to(0.5 * X + 0.3 * Z, V0.shape).astype(float).copy()
+    psi0 = _outgoing_3d(*axes)
+    f = wl.Pulse(E0=0.06, omega=0.25, cycles=2).at_midpoints(0.0, 0.05, 30)
+    o = ot.Problem3D(*axes, V0=V0, W=W).propagate(psi0, 0.05, f)
+    plan = s.Plan([32, 16, 64], [a.L for a in axes], R0=[a.R0 for a in axes], theta=0.5, charge=1.0, a2=0.64)
+    v0d = torch.from_numpy(V0).cuda()
+    wd = torch.from_numpy(W).cuda()
+    plan.set_potential(v0d, wd)
+    psi = torch.from_numpy(psi0).cuda()
+    plan.propagate(psi, 0.05, 30, torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    assert rel_l2(psi.cpu().numpy(), o) < TOL64
+    plan.close()
+
+
+def test_3d_static_scratch_path_is_bit_identical():
+    s = _sofft()
+    axes = _axes(64, 32, 32)
+    psi0 = _outgoing_3d(*axes)
+    f = wl.Pulse().at_midpoints(0.0, 0.05, 10)
+    a = run_gpu_3d(axes, psi0, 0.05, f, s.C128)
+    b = run_gpu_3d(axes, psi0, 0.05, f, s.C128, static=True)
+    assert np.array_equal(a, b)
+
+
+def test_3d_norm2_and_workspace():
+    s = _sofft()
+    plan = s.Plan([32, 16, 64], [6.4, 3.2, 12.8], R0=[2.5, 1.2, 5.0])
+    rng = np.random.default_rng(2)
+    a = rng.normal(size=(64, 16, 32)) + 1j * rng.normal(size=(64, 16, 32))
+    assert plan.norm2(torch.from_numpy(a).cuda()) == pytest.approx(np.sum(np.abs(a) ** 2), rel=1e-14)
+    assert plan.workspace_size(0) >= 64 * 16 * 32 * 16
+    with pytest.raises(s.SofftError):
+        plan.workspace_size(4)      # the stationary solver takes 2D plans
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_3d_full_workload_against_stored_oracle_checkpoints(dtype):
+    """The 3D workload (256^3, h = 0.4, soft-core, pulse along x, SECS on all
+    six faces) for 100 steps against the FP64 oracle's state after 25, 50 and
+    100 steps, stored at 8192 seeded points with the squared norm
+    (tests/golden/make_tdse_3d_256_checkpoints.py calls only the oracle)."""
+    import os
+    s = _sofft()
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "tdse_3d_256_checkpoints.npz"))
+    c = wl.TDSE_3D
+    plan = s.Plan([c.n] * 3, [c.L] * 3, R0=[c.R0] * 3, theta=c.theta, charge=c.charge, a2=c.a2,
+                  dtype=s.C128 if dtype == "c128" else s.C64)
+    x = plan.nodes(0)
+    psi0 = wl.gaussian_3d(x, x, x, **wl.packet_params_3d(int(gold["packet_seed"])))
+    psi = torch.from_numpy(psi0.astype(np.complex128 if dtype == "c128" else np.complex64)).cuda()
+    f = torch.from_numpy(c.pulse.at_midpoints(0.0, c.dt, int(gold["steps"][-1]))).cuda()
+    tol = TOL64 if dtype == "c128" else TOL32
+    done = 0
+    for k, step in enumerate(gold["steps"]):
+        step = int(step)
+        print(f"3D 256^3 {dtype}: steps {done}..{step}", flush=True)
+        plan.propagate(psi, c.dt, step - done, f[done:step])
+        done = step
+        torch.cuda.synchronize()
+        got = psi.cpu().numpy().astype(np.complex128).ravel()[gold["index"]]
+        err = rel_l2(got, gold["samples"][k])
+        nerr = abs(plan.norm2(psi) - gold["norm2"][k]) / gold["norm2"][k]
+        print(f"   step {step}: rel L2 on samples {err:.3e}, norm^2 rel error {nerr:.3e}", flush=True)
+        assert err < tol and nerr < tol
+    plan.close()
