@@ -38,7 +38,7 @@ def measured_traffic(kernel):
         return None
     rec = json.load(open(path))
     srcs = [os.path.join(ROOT, "paper_1505_06707_amd", "csrc", n)
-            for n in ("tdse.hip", "line_fft.hpp", "potential.hpp", "cx.hpp")]
+            for n in ("tdse.hip", "passes.hpp", "line_fft.hpp", "potential.hpp", "cx.hpp")]
     sha = hashlib.sha256(b"".join(open(p, "rb").read() for p in srcs)).hexdigest()
     if rec.get("kernel") != kernel or rec.get("source_sha256") != sha:
         return None
