@@ -14,6 +14,9 @@ Readings:
   f - A x and restart from it while it still exceeds rtol.
 * 2D: K = (k_x^2 + k_y^2)/2 and C = C_x (x) I + I (x) C_y as in the TDSE;
   U = V0(z_x, z_y) + f x with the field value f (zero once the pulse is over).
+* 3D (Sec. III: the FFT preconditioner generalises to the many-dimensional
+  case): K = (k_x^2 + k_y^2 + k_z^2)/2, C = C_x + C_y + C_z, arrays
+  [nz][ny][nx]; P^-1 = F^-1 (K - E)^-1 F with the full 3D transform.
 * The preconditioner's divisor k^2/2 - E is used as printed.  The optional
   shift eta (divisor k^2/2 - E - i eta) is not from the paper; eta = 0 is the
   printed form.  The shifted symbol is still even in k, so P^-1 stays
@@ -37,27 +40,36 @@ class Operator:
         self.eta = float(eta)
         if len(axes) == 1:
             self.K = axes[0].k ** 2 / 2
-        else:
+        elif len(axes) == 2:
             ax, ay = axes
             self.K = (ax.k[None, :] ** 2 + ay.k[:, None] ** 2) / 2
+        else:
+            ax, ay, az = axes
+            self.K = (ax.k[None, None, :] ** 2 + ay.k[None, :, None] ** 2 + az.k[:, None, None] ** 2) / 2
 
     def _F(self, v):
-        if len(self.axes) == 1:
-            return grid.forward(v, self.axes[0].L)
-        ax, ay = self.axes
-        return grid.forward(grid.forward(v, ax.L, axis=1), ay.L, axis=0)
+        # axis a of the grid is array axis ndim - 1 - a (x fastest)
+        nd = len(self.axes)
+        for a, ax in enumerate(self.axes):
+            v = grid.forward(v, ax.L, axis=nd - 1 - a)
+        return v
 
     def _Finv(self, v):
-        if len(self.axes) == 1:
-            return grid.inverse(v, self.axes[0].L)
-        ax, ay = self.axes
-        return grid.inverse(grid.inverse(v, ay.L, axis=0), ax.L, axis=1)
+        nd = len(self.axes)
+        for a, ax in reversed(list(enumerate(self.axes))):
+            v = grid.inverse(v, ax.L, axis=nd - 1 - a)
+        return v
 
     def _C(self, v):
-        if len(self.axes) == 1:
-            return self.axes[0].C @ v
-        ax, ay = self.axes
-        return (ax.C @ v.T).T + ay.C @ v
+        # C = sum over axes of C_a acting along axis a
+        nd = len(self.axes)
+        out = np.zeros_like(v, dtype=complex)
+        for a, ax in enumerate(self.axes):
+            w = np.moveaxis(v, nd - 1 - a, 0)
+            shape = w.shape
+            cw = (ax.C @ w.reshape(shape[0], -1)).reshape(shape)
+            out = out + np.moveaxis(cw, 0, nd - 1 - a)
+        return out
 
     def matvec(self, v):
         """A v = F^-1 K F v + C v + (U - E) v (Sec. III, Eq. linsys)."""

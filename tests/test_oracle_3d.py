@@ -90,3 +90,53 @@ def test_time_reversal_3d():
     fwd = prob.propagate(psi0, 0.05, f)
     back = prob.propagate(fwd, -0.05, f[::-1])
     assert np.linalg.norm(back - psi0) / np.linalg.norm(psi0) < 1e-11
+
+
+# ---- stationary equation in 3D (Sec. III, Eq. linsys; the FFT preconditioner
+# of Eq. PreconFFT with the full 3D transform)
+
+def _op3(E, kinds=(contour.SECS, contour.SECS, contour.TFECS), Zc=1.0, n=(8, 6, 4)):
+    axes = [_axis(n[0], 6.4, kind=kinds[0], R0=2.0), _axis(n[1], 4.8, kind=kinds[1], R0=1.5),
+            _axis(n[2], 4.0, kind=kinds[2], R0=1.2)]
+    ax, ay, az = axes
+    V = tdse.softcore(Zc, 0.64, ax.z[None, None, :], ay.z[None, :, None], az.z[:, None, None])
+    from oracle import sse
+    return axes, sse.Operator(axes, V, E)
+
+
+def test_3d_operator_is_complex_symmetric_and_cocg_matches_dense():
+    from oracle import sse
+    _, op = _op3(0.7)
+    A = op.dense()
+    assert np.allclose(A, A.T, atol=1e-13)
+    assert not np.allclose(A, A.conj().T, atol=1e-6)
+    rng = np.random.default_rng(13)
+    f = rng.normal(size=(4, 6, 8)) + 1j * rng.normal(size=(4, 6, 8))
+    x, it, res = sse.cocg(op, f, rtol=1e-13)
+    xd = sse.dense_solve(op, f)
+    assert res <= 1e-13
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
+
+
+def test_3d_matvec_approximates_the_continuous_operator():
+    """ECS off, smooth f: A f = -1/2 lap f + (U - E) f to spectral accuracy."""
+    from oracle import sse
+    axes = [_axis(n, 0.4 * n, kind=contour.OFF) for n in (56, 52, 48)]
+    ax, ay, az = axes
+    X, Y, Z = ax.x[None, None, :], ay.x[None, :, None], az.x[:, None, None]
+    V = tdse.softcore(1.0, 0.64, X.astype(complex), Y.astype(complex), Z.astype(complex))
+    op = sse.Operator(axes, V, 0.4)
+    r2 = X ** 2 + Y ** 2 + Z ** 2
+    f = np.exp(-r2 / 2)
+    lap = (r2 - 3) * f
+    assert np.max(np.abs(op.matvec(f) - (-0.5 * lap + (V - 0.4) * f))) < 1e-11
+
+
+def test_3d_preconditioner_is_the_exact_inverse_without_ecs_and_potential():
+    from oracle import sse
+    _, op = _op3(0.37, kinds=(contour.OFF,) * 3, Zc=0.0)
+    rng = np.random.default_rng(14)
+    v = rng.normal(size=(4, 6, 8)) + 1j * rng.normal(size=(4, 6, 8))
+    assert np.allclose(op.precond(op.matvec(v)), v, atol=1e-12)
+    x, it, res = sse.cocg(op, v, rtol=1e-12)
+    assert it == 1 and res < 1e-12
