@@ -538,8 +538,8 @@ sofft_status sofft_workspace_size(const sofft_plan* plan, int32_t n_energies, in
     set_error("bad argument to sofft_workspace_size");
     return SOFFT_EINVAL;
   }
-  if (n_energies > 0 && (plan->prob.ndim != 2 || plan->prob.dtype != SOFFT_C128)) {
-    set_error("the stationary solver works on 2D complex128 plans");
+  if (n_energies > 0 && (plan->prob.ndim < 2 || plan->prob.dtype != SOFFT_C128)) {
+    set_error("the stationary solver works on 2D and 3D complex128 plans");
     return SOFFT_EUNSUPPORTED;
   }
   *bytes = int64_t(plan_ws_layout(*plan, n_energies).total);

@@ -28,111 +28,9 @@
 #include "line_fft.hpp"
 #include "potential.hpp"
 #include "internal.hpp"
+#include "sse.hpp"
 
 namespace sofft {
-
-enum CocgState : int {
-  kActive = 0,     // iterating
-  kCheck = 1,      // recurrence residual below rtol: true residual pending
-  kDone = 2,       // true residual below rtol
-  kMaxit = 3,      // iteration limit reached
-  kBreakdown = 4,  // rho or p^T A p vanished twice in a row
-};
-
-struct CocgScalars {
-  cx<double> rho, alpha, beta;
-  double rr, ff, true_res;
-  int state, iters, first, restarts;
-  // flexible COCG with the learned correction
-  double best_rr;
-  int since, fell_back, fb_pending, pad_;
-};
-
-struct SseArgs {
-  int nx, ny, nE;
-  size_t vec;                  // n_x n_y
-  cx<double>* x;               // solution (caller's buffer)
-  cx<double>* r;
-  cx<double>* p;
-  cx<double>* w;
-  cx<double>* z;
-  cx<double>* s;               // preconditioner spectrum; also w1 of A p
-  const cx<double>* f;
-  int f_per_energy;
-  const cx<double>* V;         // U on the grid, [n_y][n_x]
-  const double* E;             // [nE]
-  const double* eta;           // [nE] shift of the preconditioner's divisor (K - E - i eta), or null
-  // banded ECS eigen-preconditioner (Eq. PreconFFT_ECS) instead of Eq. PreconFFT when banded = 1;
-  // per axis the tables of ensure_bands (x: rows of the grid, y: columns)
-  int banded;
-  const cx<double>* bx_lam;
-  const cx<double>* bx_xr;
-  const cx<double>* bx_xc;
-  const int* bx_start;
-  const int* bx_width;
-  const cx<double>* by_lam;
-  const cx<double>* by_xr;
-  const cx<double>* by_xc;
-  const int* by_start;
-  const int* by_width;
-  CocgScalars* sc;             // [nE]
-  double* part_rr;             // [nE][nblk_row]
-  cx<double>* part_rz;         // [nE][nblk_row]
-  cx<double>* part_pw;         // [nE][nblk_col]
-  int nblk_row, nblk_col;
-  const cx<double>* twx;       // FFT stage twiddles along x and y
-  const cx<double>* twy;
-  double Lx, Ly;
-  int j0x, mx, j0y, my;        // ECS strips
-  const cx<double>* cx_strip;  // [C_{j,j-1} | C_{j,j} | C_{j,j+1}] on the x-strip
-  const cx<double>* cy_strip;
-  int lds_line_x, lds_line_y;
-  // learned correction (flexible COCG): off when learned = 0
-  int learned, patience;
-  cx<double>* part_rzo;        // [nE][nblk_row]: r^T z_old
-  int* active;                 // [nE]: energies the network corrects this round
-  double* lp_scale;            // [nE]: rms of r
-  double* E_dev;               // [nE] workspace copies of the energies and shifts
-  double* eta_dev;
-};
-
-enum RowMode : int { kRowIter = 0, kRowTrue = 1 };          // K1: input p (updated) or x
-enum UpdMode : int { kUpdIter = 0, kUpdInit = 1, kUpdTrue = 2, kUpdCopy = 3 };
-
-__device__ __forceinline__ double kval(int e, int n, double L) {
-  const int m = e < n / 2 ? e : e - n;
-  return 6.283185307179586476925286766559 * double(m) / L;
-}
-
-__device__ __forceinline__ cx<double> shfl_xor(cx<double> v, int mask) {
-  return {__shfl_xor(v.re, mask), __shfl_xor(v.im, mask)};
-}
-
-// Sum over the block in a fixed order (wavefront butterflies, then the
-// wavefront sums in index order); result valid in thread 0.  red: LDS
-// scratch of blockDim.x/64 elements.  Contains block barriers.
-__device__ __forceinline__ cx<double> block_sum(cx<double> v, cx<double>* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = v + shfl_xor(v, o);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  cx<double> acc{0.0, 0.0};
-  if (threadIdx.x == 0)
-    for (int w = 0; w < int(blockDim.x >> 6); ++w) acc = acc + red[w];
-  return acc;
-}
-
-// C applied on the strip of a line held in LDS (plain layout): element e's
-// row of C times the line, zero off the strip.
-__device__ __forceinline__ cx<double> c_apply(const LineLDS<double>& L, int e, int n, int j0, int m,
-                                              const cx<double>* cs) {
-  int p = e - j0;
-  if (p < 0) p += n;
-  if (p >= m) return {0.0, 0.0};
-  const int em = e == 0 ? n - 1 : e - 1, ep = e + 1 == n ? 0 : e + 1;
-  return cmul(cs[p], L[em]) + cmul(cs[m + p], L[e]) + cmul(cs[2 * m + p], L[ep]);
-}
 
 // Threads per block.  Column kernels (K2, K5): at most 1024; lines of 512
 // points take 512 (4 adjacent columns, 64-byte segments), see sse_col_threads.
@@ -474,7 +372,7 @@ __global__ void k_sse_lp_gate(SseArgs a, int want) {
   const CocgScalars& sc = a.sc[e];
   const bool on = sc.state == want && !sc.fell_back;
   double rr = 0.0;
-  for (int b = 0; b < a.nblk_row; ++b) rr += a.part_rr[size_t(e) * a.nblk_row + b];
+  for (int b = 0; b < a.nred_row; ++b) rr += a.part_rr[size_t(e) * a.nblk_row + b];
   a.active[e] = (on && rr > 0.0) ? 1 : 0;
   a.lp_scale[e] = sqrt(rr / double(a.vec));
 }
@@ -508,7 +406,7 @@ __global__ void k_sse_init(SseArgs a) {
   CocgScalars& sc = a.sc[e];
   double ff = 0.0;
   cx<double> rz{0.0, 0.0};
-  for (int b = 0; b < a.nblk_row; ++b) {
+  for (int b = 0; b < a.nred_row; ++b) {
     ff += a.part_rr[size_t(e) * a.nblk_row + b];
     rz = rz + a.part_rz[size_t(e) * a.nblk_row + b];
   }
@@ -534,7 +432,7 @@ __global__ void k_sse_alpha(SseArgs a) {
   CocgScalars& sc = a.sc[e];
   if (sc.state != kActive) return;
   cx<double> pw{0.0, 0.0};
-  for (int b = 0; b < a.nblk_col; ++b) pw = pw + a.part_pw[size_t(e) * a.nblk_col + b];
+  for (int b = 0; b < a.nred_col; ++b) pw = pw + a.part_pw[size_t(e) * a.nblk_col + b];
   if (cabs2(pw) == 0.0) {
     sc.alpha = {0.0, 0.0};
     sc.state = kBreakdown;
@@ -559,7 +457,7 @@ __global__ void k_sse_beta(SseArgs a, double rtol, int maxit) {
   if (sc.state != kActive) return;
   double rr = 0.0;
   cx<double> rz{0.0, 0.0};
-  for (int b = 0; b < a.nblk_row; ++b) {
+  for (int b = 0; b < a.nred_row; ++b) {
     rr += a.part_rr[size_t(e) * a.nblk_row + b];
     rz = rz + a.part_rz[size_t(e) * a.nblk_row + b];
   }
@@ -592,7 +490,7 @@ __global__ void k_sse_beta(SseArgs a, double rtol, int maxit) {
       return;
     }
     cx<double> rzo{0.0, 0.0};
-    for (int b = 0; b < a.nblk_row; ++b) rzo = rzo + a.part_rzo[size_t(e) * a.nblk_row + b];
+    for (int b = 0; b < a.nred_row; ++b) rzo = rzo + a.part_rzo[size_t(e) * a.nblk_row + b];
     sc.beta = cdiv(rz - rzo, sc.rho);
     sc.rho = rz;
     return;
@@ -621,7 +519,7 @@ __global__ void k_sse_true(SseArgs a, double rtol, int maxit) {
   if (sc.state != kCheck) return;
   double rr = 0.0;
   cx<double> rz{0.0, 0.0};
-  for (int b = 0; b < a.nblk_row; ++b) {
+  for (int b = 0; b < a.nred_row; ++b) {
     rr += a.part_rr[size_t(e) * a.nblk_row + b];
     rz = rz + a.part_rz[size_t(e) * a.nblk_row + b];
   }
@@ -643,20 +541,21 @@ __global__ void k_sse_true(SseArgs a, double rtol, int maxit) {
   }
 }
 
-// U on the grid: soft-core at (z_x, z_y) plus field * x, or a caller's V0
-// (v0 non-null) and W (w non-null) in their places.
-__global__ void k_sse_potential(cx<double>* V, int nx, int ny, const cx<double>* zx, const cx<double>* zy,
-                                const double* x, double charge, double a2, double field, const cx<double>* v0,
-                                const double* w) {
+// U on the grid: soft-core at (z_x, z_y[, z_z]) plus field * x, or a caller's V0
+// (v0 non-null) and W (w non-null) in their places.  zz null: a 2D grid (nz = 1).
+__global__ void k_sse_potential(cx<double>* V, int nx, int ny, int nz, const cx<double>* zx, const cx<double>* zy,
+                                const cx<double>* zz, const double* x, double charge, double a2, double field,
+                                const cx<double>* v0, const double* w) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= size_t(nx) * ny) return;
-  const int jx = int(i % nx), jy = int(i / nx);
+  if (i >= size_t(nx) * ny * nz) return;
+  const int jx = int(i % nx), jy = int((i / nx) % ny), jz = int(i / (size_t(nx) * ny));
   const double fw = field * (w ? w[i] : x[jx]);
   if (v0) {
     V[i] = v0[i] + cx<double>{fw, 0.0};
     return;
   }
-  const cx<double> s = cmul(zx[jx], zx[jx]) + cmul(zy[jy], zy[jy]) + cx<double>{a2, 0.0};
+  cx<double> s = cmul(zx[jx], zx[jx]) + cmul(zy[jy], zy[jy]) + cx<double>{a2, 0.0};
+  if (zz) s = s + cmul(zz[jz], zz[jz]);
   V[i] = potential_value(s, charge, fw);
 }
 
@@ -681,7 +580,6 @@ static sofft_status sse_set_lds(K kernel, size_t bytes) {
   return bytes > 65536 ? raise_lds_limit(reinterpret_cast<const void*>(kernel), 150 * 1024) : SOFFT_OK;
 }
 
-enum SseKernel { kK1, kK2, kK4, kK5, kK6 };
 
 // Lines per block: up to 1024 threads (512 for the radix-3 shapes, which use
 // more registers) and within the LDS budget.
@@ -761,8 +659,6 @@ static sofft_status sse_launch(SseKernel k, const SseArgs& a, int want, int mode
   return tm.end(s);
 }
 
-using SseLauncher = sofft_status (*)(SseKernel, const SseArgs&, int, int, hipStream_t, Timing&);
-
 // Square grids and the rectangular shapes the tests use; more pairs can be
 // added here.
 static SseLauncher sse_launcher(int64_t nx, int64_t ny) {
@@ -786,6 +682,14 @@ static SseSizes sse_sizes(const Plan& p) {
   const Axis& X = p.ax[0];
   const Axis& Y = p.ax[1];
   SseSizes z;
+  if (p.prob.ndim == 3) {
+    const Axis& Z = p.ax[2];
+    z.vec = size_t(X.n) * Y.n * Z.n;
+    z.bytes_vec = z.vec * sizeof(cx<double>);
+    z.llx = z.lly = 0;
+    sse3_blocks(X.n, Y.n, Z.n, &z.nbr, &z.nbc);
+    return z;
+  }
   z.vec = size_t(X.n) * Y.n;
   z.bytes_vec = z.vec * sizeof(cx<double>);
   z.llx = int(std::max<int64_t>(sse_lds_elems(X.n), 64));
@@ -820,8 +724,11 @@ static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipSt
     q += r256(b);
     return r;
   };
+  const bool three = p.prob.ndim == 3;
+  const Axis& Z = p.ax[three ? 2 : 1];
   a.nx = int(X.n);
   a.ny = int(Y.n);
+  a.nz = three ? int(Z.n) : 1;
   a.nE = nE;
   a.vec = vec;
   a.r = reinterpret_cast<cx<double>*>(take(bytes_vec * nE));
@@ -842,6 +749,9 @@ static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipSt
   a.eta_dev = reinterpret_cast<double*>(take(sizeof(double) * nE));
   a.nblk_row = nbr;
   a.nblk_col = nbc;
+  // the 3D passes reduce their partials into the first slot of each energy
+  a.nred_row = three ? 1 : nbr;
+  a.nred_col = three ? 1 : nbc;
   a.twx = static_cast<const cx<double>*>(X.tw64.p);
   a.twy = static_cast<const cx<double>*>(Y.tw64.p);
   a.Lx = X.L;
@@ -852,25 +762,39 @@ static sofft_status sse_prepare(Plan& p, int nE, double field, SseArgs& a, hipSt
   a.my = int(Y.m);
   a.cx_strip = static_cast<const cx<double>*>(X.cstrip64.p);
   a.cy_strip = static_cast<const cx<double>*>(Y.cstrip64.p);
+  if (three) {
+    a.twz = static_cast<const cx<double>*>(Z.tw64.p);
+    a.Lz = Z.L;
+    a.j0z = int(Z.j0);
+    a.mz = int(Z.m);
+    a.cz_strip = static_cast<const cx<double>*>(Z.cstrip64.p);
+  }
   a.lds_line_x = llx;
   a.lds_line_y = lly;
   const int threads = 256;
   k_sse_potential<<<int((vec + threads - 1) / threads), threads, 0, s>>>(
-      V, a.nx, a.ny, static_cast<const cx<double>*>(X.z_dev.p), static_cast<const cx<double>*>(Y.z_dev.p),
-      static_cast<const double*>(X.x_dev.p), p.prob.charge, p.prob.a2, field,
+      V, a.nx, a.ny, a.nz, static_cast<const cx<double>*>(X.z_dev.p), static_cast<const cx<double>*>(Y.z_dev.p),
+      three ? static_cast<const cx<double>*>(Z.z_dev.p) : nullptr, static_cast<const double*>(X.x_dev.p),
+      p.prob.charge, p.prob.a2, field,
       static_cast<const cx<double>*>(p.user_v0), p.user_w);
   SOFFT_HIP_TRY(hipGetLastError());
   return SOFFT_OK;
 }
 
+static SseLauncher launcher_of(const Plan& p) {
+  if (p.prob.ndim == 3) return sse3_launcher(p.ax[0].n, p.ax[1].n, p.ax[2].n);
+  return sse_launcher(p.ax[0].n, p.ax[1].n);
+}
+
 static sofft_status sse_check_plan(const Plan& p) {
-  if (p.prob.ndim != 2 || p.prob.dtype != SOFFT_C128) {
-    set_error("the stationary solver works on 2D complex128 plans");
+  if ((p.prob.ndim != 2 && p.prob.ndim != 3) || p.prob.dtype != SOFFT_C128) {
+    set_error("the stationary solver works on 2D and 3D complex128 plans");
     return SOFFT_EUNSUPPORTED;
   }
-  if (!sse_launcher(p.ax[0].n, p.ax[1].n)) {
-    set_error("no stationary-solver kernels for a " + std::to_string(p.ax[0].n) + " x " +
-              std::to_string(p.ax[1].n) + " grid");
+  if (!launcher_of(p)) {
+    std::string shape = std::to_string(p.ax[0].n) + " x " + std::to_string(p.ax[1].n);
+    if (p.prob.ndim == 3) shape += " x " + std::to_string(p.ax[2].n);
+    set_error("no stationary-solver kernels for a " + shape + " grid");
     return SOFFT_EUNSUPPORTED;
   }
   return SOFFT_OK;
@@ -901,6 +825,10 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
                        int patience, const double* eta_host, int banded) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
+  if (p.prob.ndim == 3 && (lp || banded)) {
+    set_error("the learned correction and the banded preconditioner work on 2D grids");
+    return SOFFT_EUNSUPPORTED;
+  }
   SseArgs a{};
   if ((st = sse_prepare(p, nE, field, a, s)) != SOFFT_OK) return st;
   a.learned = lp ? 1 : 0;
@@ -916,7 +844,7 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
     a.eta = a.eta_dev;
   }
   if (banded && (st = use_bands(p, a)) != SOFFT_OK) return st;
-  SseLauncher L = sse_launcher(p.ax[0].n, p.ax[1].n);
+  SseLauncher L = launcher_of(p);
   Timing& tm = p.timing;
   const int sb = (nE + 63) / 64;
   // learned correction of z = P^-1 r for the energies in state `want`, then r^T z
@@ -1053,6 +981,10 @@ sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double
                        int banded) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
+  if (p.prob.ndim == 3 && banded) {
+    set_error("the banded preconditioner works on 2D grids");
+    return SOFFT_EUNSUPPORTED;
+  }
   SseArgs a{};
   if ((st = sse_prepare(p, 1, field, a, s)) != SOFFT_OK) return st;
   SOFFT_HIP_TRY(hipMemcpyAsync(a.E_dev, &E, sizeof(double), hipMemcpyHostToDevice, s));
@@ -1065,7 +997,7 @@ sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double
   CocgScalars c{};
   c.state = kActive;
   SOFFT_HIP_TRY(hipMemcpyAsync(a.sc, &c, sizeof(c), hipMemcpyHostToDevice, s));
-  SseLauncher L = sse_launcher(p.ax[0].n, p.ax[1].n);
+  SseLauncher L = launcher_of(p);
   const size_t bytes = a.vec * sizeof(cx<double>);
   if (op == 0) {
     a.x = const_cast<cx<double>*>(static_cast<const cx<double>*>(v));

@@ -1,0 +1,187 @@
+"""GPU parity of the stationary solver on 3D grids (Sec. III; the FFT
+preconditioner of Eq. PreconFFT with the full 3D transform) against the FP64
+oracle: A v and P^-1 v on seeded vectors, element by element, over shapes
+that mix the line lengths of every axis and both contours; COCG solutions
+against dense Gaussian elimination on 16^3; and the oracle's true residual of
+GPU solutions on larger grids, with the divisor shift, a field and a caller's
+potential.  Tolerance: relative L2 <= 1e-13 for the applications (FP64,
+different summation order), the requested rtol for solutions."""
+import numpy as np
+import pytest
+
+from oracle import sse as osse
+from oracle import tdse as ot
+from paper_1505_06707_amd import workloads as wl
+from tests.helpers import CONTOURS, rel_l2
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _setup(shape, h=0.4, frac=0.8, theta=0.5, charge=1.0, a2=0.64, E=0.7, field=0.0, kind="secs", eta=0.0):
+    from paper_1505_06707_amd import sofft
+    L = [n * h for n in shape]
+    R0 = [frac * l / 2 for l in L]
+    plan = sofft.Plan(list(shape), L, R0=R0, theta=theta, charge=charge, a2=a2, contour=CONTOURS[kind][1])
+    axes = [ot.Axis(n, l, kind=CONTOURS[kind][0], R0=r, theta=theta) for n, l, r in zip(shape, L, R0)]
+    ax, ay, az = axes
+    V = (ot.softcore(charge, a2, ax.z[None, None, :], ay.z[None, :, None], az.z[:, None, None])
+         + field * ax.x[None, None, :])
+    return plan, osse.Operator(tuple(axes), V, E, eta=eta), axes
+
+
+def _rand(shape, seed):
+    rng = np.random.default_rng(seed)
+    sh = tuple(reversed(shape))
+    return rng.normal(size=sh) + 1j * rng.normal(size=sh)
+
+
+SHAPES = [(16, 16, 16), (64, 32, 16), (16, 64, 32), (32, 16, 128), (128, 64, 32), (256, 16, 16), (16, 16, 512)]
+
+
+@pytest.mark.parametrize("kind", ["secs", "tfecs"])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("op", [0, 1])
+def test_apply_matches_oracle_3d(shape, op, kind):
+    print(f"sse3d apply op={op} {shape} {kind}", flush=True)
+    plan, oop, _ = _setup(shape, E=0.83, field=0.01, kind=kind)
+    v = _rand(shape, sum(shape) + op)
+    w = plan.sse_apply(op, torch.from_numpy(v).cuda(), 0.83, field=0.01)
+    torch.cuda.synchronize()
+    want = oop.matvec(v) if op == 0 else oop.precond(v)
+    err = rel_l2(w.cpu().numpy(), want)
+    print(f"   rel L2 {err:.2e}", flush=True)
+    assert err < 1e-13
+    plan.close()
+
+
+def test_shifted_preconditioner_matches_oracle_3d():
+    shape = (32, 64, 16)
+    plan, oop, _ = _setup(shape, E=1.1, eta=0.35)
+    v = _rand(shape, 5)
+    w = plan.sse_apply(1, torch.from_numpy(v).cuda(), 1.1, eta=0.35)
+    torch.cuda.synchronize()
+    assert rel_l2(w.cpu().numpy(), oop.precond(v)) < 1e-13
+    plan.close()
+
+
+def test_solve_matches_dense_gaussian_elimination_3d():
+    shape = (16, 16, 16)
+    print("sse3d dense 16^3", flush=True)
+    plan, _, axes = _setup(shape, h=0.5)
+    rng = np.random.default_rng(9)
+    f = rng.normal(size=(16, 16, 16)) + 1j * rng.normal(size=(16, 16, 16))
+    Es = [0.1, 0.9, 1.7]
+    x, stats, code = plan.sse_solve(torch.from_numpy(f).cuda(), Es, rtol=1e-12, maxit=3000)
+    assert code == 0
+    xs = x.cpu().numpy()
+    ax, ay, az = axes
+    V = ot.softcore(1.0, 0.64, ax.z[None, None, :], ay.z[None, :, None], az.z[:, None, None])
+    for j, E in enumerate(Es):
+        xd = osse.dense_solve(osse.Operator(tuple(axes), V, E), f)
+        err = rel_l2(xs[j], xd)
+        print(f"   E={E}: {stats[j]['iterations']} iterations, rel L2 to dense {err:.2e}", flush=True)
+        assert stats[j]["rel_residual"] <= 1e-12
+        assert err < 1e-9
+    plan.close()
+
+
+def _source_3d(shape, seed):
+    """Smooth seeded source: complex white noise filtered by a periodic Gaussian
+    of sigma = 2 cells, unit 2-norm (the 2D recipe on three axes)."""
+    rng = np.random.default_rng(seed)
+    sh = tuple(reversed(shape))
+    w = rng.normal(size=sh) + 1j * rng.normal(size=sh)
+    filt = 1.0
+    for a, n in enumerate(sh):
+        k = 2 * np.pi * np.fft.fftfreq(n)
+        g = np.exp(-(2.0 * k) ** 2 / 2)
+        filt = filt * g.reshape([-1 if b == a else 1 for b in range(3)])
+    s = np.fft.ifftn(np.fft.fftn(w) * filt)
+    return s / np.linalg.norm(s)
+
+
+@pytest.mark.parametrize("shape,kind", [((32, 32, 32), "secs"), ((64, 32, 32), "tfecs"),
+                                        ((64, 64, 64), "secs")])
+def test_solve_true_residual_by_the_oracle_3d(shape, kind):
+    print(f"sse3d solve {shape} {kind}", flush=True)
+    plan, _, axes = _setup(shape, kind=kind)
+    f = -_source_3d(shape, 21)
+    Es = [0.05, 0.6, 1.3, 2.0]
+    x, stats, code = plan.sse_solve(torch.from_numpy(f).cuda(), Es, rtol=1e-8)
+    assert code == 0
+    xs = x.cpu().numpy()
+    ax, ay, az = axes
+    V = ot.softcore(1.0, 0.64, ax.z[None, None, :], ay.z[None, :, None], az.z[:, None, None])
+    for j, E in enumerate(Es):
+        op = osse.Operator(tuple(axes), V, E)
+        res = float(np.linalg.norm(f - op.matvec(xs[j])) / np.linalg.norm(f))
+        print(f"   E={E}: {stats[j]['iterations']} iterations ({stats[j]['restarts']} restarts), "
+              f"oracle true residual {res:.2e}", flush=True)
+        assert stats[j]["status"] == 0 and res <= 1e-8 * (1 + 1e-3)
+    plan.close()
+
+
+def test_iterations_match_the_oracle_cocg_3d():
+    """The same recurrences in the same order of operations up to summation
+    order: iteration counts agree with the oracle's COCG to within a few."""
+    shape = (32, 32, 32)
+    plan, oop, _ = _setup(shape, E=0.9)
+    f = -_source_3d(shape, 22)
+    x, stats, code = plan.sse_solve(torch.from_numpy(f).cuda(), [0.9], rtol=1e-8)
+    assert code == 0
+    xo, it, res = osse.cocg(oop, f, rtol=1e-8)
+    print(f"   GPU {stats[0]['iterations']} oracle {it}", flush=True)
+    assert abs(stats[0]["iterations"] - it) <= max(3, 0.03 * it)
+    assert rel_l2(x[0].cpu().numpy(), xo) < 1e-6
+
+
+def test_field_shift_and_caller_potential_3d():
+    """A field (static part f x), per-energy divisor shifts, and a caller's V0
+    in place of the soft-core: each solve checked by the oracle's residual."""
+    shape = (32, 16, 32)
+    plan, _, axes = _setup(shape)
+    ax, ay, az = axes
+    f = -_source_3d(shape, 23)
+    Es = [0.3, 1.2]
+    Vs = ot.softcore(1.0, 0.64, ax.z[None, None, :], ay.z[None, :, None], az.z[:, None, None])
+    # field
+    x, st, code = plan.sse_solve(torch.from_numpy(f).cuda(), Es, field=0.02, rtol=1e-9)
+    assert code == 0
+    for j, E in enumerate(Es):
+        op = osse.Operator(tuple(axes), Vs + 0.02 * ax.x[None, None, :], E)
+        assert np.linalg.norm(f - op.matvec(x[j].cpu().numpy())) / np.linalg.norm(f) <= 1e-9 * (1 + 1e-3)
+    # shifts
+    x, st, code = plan.sse_solve(torch.from_numpy(f).cuda(), Es, rtol=1e-9, eta=[0.2, 0.5])
+    assert code == 0
+    for j, E in enumerate(Es):
+        op = osse.Operator(tuple(axes), Vs, E)
+        assert np.linalg.norm(f - op.matvec(x[j].cpu().numpy())) / np.linalg.norm(f) <= 1e-9 * (1 + 1e-3)
+    # a caller's V0: a deeper, wider well on the contour
+    V0 = ot.softcore(1.5, 1.2, ax.z[None, None, :], ay.z[None, :, None], az.z[:, None, None])
+    V0t = torch.from_numpy(np.ascontiguousarray(V0)).cuda()
+    plan.set_potential(V0t, None)
+    x, st, code = plan.sse_solve(torch.from_numpy(f).cuda(), Es, rtol=1e-9)
+    assert code == 0
+    for j, E in enumerate(Es):
+        op = osse.Operator(tuple(axes), V0, E)
+        assert np.linalg.norm(f - op.matvec(x[j].cpu().numpy())) / np.linalg.norm(f) <= 1e-9 * (1 + 1e-3)
+    plan.close()
+
+
+def test_per_energy_sources_and_rejections_3d():
+    from paper_1505_06707_amd import sofft
+    shape = (16, 32, 16)
+    plan, _, axes = _setup(shape)
+    ax, ay, az = axes
+    Es = [0.4, 1.0, 1.6]
+    f = np.stack([-_source_3d(shape, 30 + j) for j in range(3)])
+    x, st, code = plan.sse_solve(torch.from_numpy(f).cuda(), Es, rtol=1e-9)
+    assert code == 0
+    V = ot.softcore(1.0, 0.64, ax.z[None, None, :], ay.z[None, :, None], az.z[:, None, None])
+    for j, E in enumerate(Es):
+        op = osse.Operator(tuple(axes), V, E)
+        assert np.linalg.norm(f[j] - op.matvec(x[j].cpu().numpy())) / np.linalg.norm(f[j]) <= 1e-9 * (1 + 1e-3)
+    with pytest.raises(sofft.SofftError):
+        plan.sse_solve(torch.from_numpy(f[0]).cuda(), Es, banded=True)   # the banded form is 2D only
+    plan.close()

@@ -137,9 +137,13 @@ def test_3d_norm2_and_workspace():
     a = rng.normal(size=(64, 16, 32)) + 1j * rng.normal(size=(64, 16, 32))
     assert plan.norm2(torch.from_numpy(a).cuda()) == pytest.approx(np.sum(np.abs(a) ** 2), rel=1e-14)
     assert plan.workspace_size(0) >= 64 * 16 * 32 * 16
-    with pytest.raises(s.SofftError):
-        plan.workspace_size(4)      # the stationary solver takes 2D plans
+    # the stationary solver's region: five vectors per energy and U
+    assert plan.workspace_size(4) - plan.workspace_size(0) >= (5 * 4 + 1) * 64 * 16 * 32 * 16
     plan.close()
+    c64 = s.Plan([32, 16, 64], [6.4, 3.2, 12.8], R0=[2.5, 1.2, 5.0], dtype=s.C64)
+    with pytest.raises(s.SofftError):
+        c64.workspace_size(4)       # the solver works in complex128
+    c64.close()
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
