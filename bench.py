@@ -265,6 +265,49 @@ def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0, extras=True, shifted=Fals
             "kernels_ms": {k: v[0] for k, v in kern.items()}, "shifted": shifted, "banded": band}
 
 
+def gpu_pcg3d(sofft, wl, torch, seed=0):
+    """Batched COCG to 1e-8 on the 3D stationary workload (128^3, 16 energies):
+    time to tolerance, iterations, the event-timed line-pass groups and their
+    algorithmic bytes."""
+    c = wl.SSE_3D
+    plan = sofft.Plan([c.n] * 3, [c.L] * 3, R0=[c.R0] * 3, theta=c.theta, charge=c.charge, a2=c.a2)
+    f = torch.from_numpy(-wl.smooth_source_3d(c.n, c.n, c.n, seed=seed)).cuda()
+    E = c.energies()
+    out = torch.empty((len(E), c.n, c.n, c.n), dtype=torch.complex128, device="cuda")
+    plan.sse_solve(f, E[:2], rtol=c.rtol, out=out[:2])       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, stats, code = plan.sse_solve(f, E, rtol=c.rtol, out=out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.timing(True)
+    plan.sse_solve(f, E, rtol=c.rtol, out=out)
+    kinds = {"xy_matvec": sofft.KERNEL_SSE_ROW_MV, "z_matvec": sofft.KERNEL_SSE_COL_MV,
+             "x_update_fft": sofft.KERNEL_SSE_ROW_UPD, "yzy_precond": sofft.KERNEL_SSE_COL_PREC,
+             "x_precond_dot": sofft.KERNEL_SSE_ROW_PREC}
+    kern = {k: plan.timing_read(v) for k, v in kinds.items()}
+    plan.timing(False)
+    plan.close()
+    its = np.array([s["iterations"] for s in stats])
+    res = np.array([s["rel_residual"] for s in stats])
+    npts = c.n ** 3
+    # algorithmic bytes per point, iteration and energy of each pass group
+    # (S = 16 B): x+y matvec 4S + 3S, z matvec 3S, update 7S, y/z/y
+    # preconditioner 6S, x preconditioner 3S; 26S in all
+    per_S = {"xy_matvec": 7, "z_matvec": 3, "x_update_fft": 7, "yzy_precond": 6, "x_precond_dot": 3}
+    total_it = int(its.sum())
+    kern_s = sum(v[0] for v in kern.values()) / 1e3
+    gbs = {k: per_S[k] * 16 * npts * total_it / (v[0] / 1e3) / 1e9 for k, v in kern.items() if v[0] > 0}
+    return {"workload": f"3D {c.n}^3, h = {c.h}, SECS, {len(E)} energies in [{c.E_lo}, {c.E_hi}]",
+            "time_to_tol_s": wall, "energies": int(len(E)), "rtol": c.rtol, "status": int(code),
+            "iterations": {"min": int(its.min()), "mean": float(its.mean()), "max": int(its.max()),
+                           "total": total_it},
+            "max_true_rel_residual": float(res.max()),
+            "us_per_energy_iteration": kern_s / total_it * 1e6,
+            "kernel_time_s": kern_s, "achieved_GBs_all_passes": 26 * 16 * npts * total_it / kern_s / 1e9,
+            "group_GBs": gbs, "kernels_ms": {k: v[0] for k, v in kern.items()}}
+
+
 def gpu_pcg_tfecs(sofft, wl, torch, n_energies=32, seed=0, shifted=False):
     """The 512^2 stationary workload on the TFECS contour (Eq. qTFECS, alpha =
     0.5), where the paper finds the plain FFT preconditioner slow: 32 energies
@@ -616,6 +659,14 @@ def main():
                 f"{tf['banded']['time_to_tol_s']:.3f} s (mean {tf['banded']['iterations']['mean']:.0f} it), "
                 f"{tf['banded']['speedup_vs_plain']:.2f}x")
 
+    pcg3d = None
+    if not args.no_pcg and not args.no_3d:
+        log("SSE 3D 128^3 batched COCG to 1e-8, 16 energies")
+        pcg3d = gpu_pcg3d(sofft, wl, torch)
+        log(f"  {pcg3d['time_to_tol_s']:.3f} s, iterations {pcg3d['iterations']['min']}.."
+            f"{pcg3d['iterations']['max']}, {pcg3d['us_per_energy_iteration']:.0f} us per energy-iteration, "
+            f"{pcg3d['achieved_GBs_all_passes']:.0f} GB/s over the passes")
+
     batch = None
     if not args.no_batch:
         log(f"batched uneven TDSE: 96 runs, c64, {args.batch_steps} steps")
@@ -666,6 +717,7 @@ def main():
         "tdse_1d": tdse1d,
         "tdse_3d": tdse3d,
         "pcg": pcg,
+        "pcg_3d": pcg3d,
         "batch": batch,
         "learned": learned,
     }

@@ -104,7 +104,8 @@ int32_t sofft_version(void);
  * 256 nodes per axis in 2D and 3D.  3D: the paper is 1D and names the
  * many-dimensional case as its next step; the step is read separably,
  * K = (k_x^2 + k_y^2 + k_z^2)/2 and e^{-iC dt} = CN(C_x) CN(C_y) CN(C_z).
- * The stationary solver and batches take 2D plans only.
+ * The stationary solver takes 2D and 3D complex128 plans (its banded
+ * preconditioner and learned correction 2D only); batches take 2D plans.
  * Returns SOFFT_EINVAL / SOFFT_EUNSUPPORTED / SOFFT_ENOMEM / SOFFT_EHIP. */
 sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out);
 
@@ -114,10 +115,10 @@ sofft_status sofft_plan_destroy(sofft_plan* plan);
 
 /* Bytes of device workspace the plan needs for sofft_propagate, sofft_norm2
  * and, with n_energies > 0, for stationary solves and applications of up to
- * n_energies energies at once (2D complex128 plans; SOFFT_EUNSUPPORTED
+ * n_energies energies at once (2D and 3D complex128 plans; SOFFT_EUNSUPPORTED
  * otherwise).  About 16 bytes per grid point for propagation (the table of
- * exp(-i V0 dt/2), room for a caller's V0), plus about 6 n_energies
- * n_x n_y 16 bytes for solves.  Host only: nothing is enqueued. */
+ * exp(-i V0 dt/2), room for a caller's V0), plus about (5 n_energies + 1) 16
+ * bytes per grid point for solves.  Host only: nothing is enqueued. */
 sofft_status sofft_workspace_size(const sofft_plan* plan, int32_t n_energies, int64_t* bytes);
 
 /* Bind a caller-owned device workspace of `bytes` bytes (256-byte aligned, on
@@ -215,11 +216,15 @@ typedef struct {
  * iterations (stagnation in finite precision); stats.restarts counts both,
  * and an energy stops as SOFFT_NOT_CONVERGED after 8 restarts.
  *   f       device, [n_y][n_x] (f_per_energy = 0, shared) or [nE][n_y][n_x]
+ *           ([n_z][n_y][n_x] and [nE][n_z][n_y][n_x] on 3D plans)
  *   E_host  host, nE energies
- *   x_out   device, [nE][n_y][n_x], written
+ *   x_out   device, [nE][n_y][n_x] ([nE][n_z][n_y][n_x] in 3D), written
  *   stats   host, nE entries (may be NULL)
- * 2D complex128 plans only.  The bound workspace must hold
- * sofft_workspace_size(plan, nE) bytes (about 6 nE n_x n_y * 16).
+ * 2D and 3D complex128 plans.  In 3D (Sec. III: the FFT preconditioner carries
+ * over to the many-dimensional case) K = (k_x^2 + k_y^2 + k_z^2)/2,
+ * C = C_x + C_y + C_z and P^-1 uses the full 3D transform.  The bound
+ * workspace must hold sofft_workspace_size(plan, nE) bytes (about
+ * (5 nE + 1) 16 bytes per grid point).
  * Blocking: returns after the solve.  Returns SOFFT_OK when every energy met
  * rtol, else SOFFT_NOT_CONVERGED / SOFFT_BREAKDOWN (per energy in stats). */
 sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
@@ -228,7 +233,7 @@ sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_ener
 
 /* One application of the stationary matrix (op 0: w = A v, Eq. linsys) or of
  * the FFT preconditioner (op 1: w = P^-1 v, Eq. PreconFFT) at energy E, on
- * device vectors [n_y][n_x].  Needs the workspace of one energy
+ * device vectors [n_y][n_x] ([n_z][n_y][n_x] on 3D plans).  Needs the workspace of one energy
  * (sofft_workspace_size(plan, 1)).  Asynchronous on the stream. */
 sofft_status sofft_sse_apply(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double field,
                              void* stream);
@@ -257,7 +262,8 @@ sofft_status sofft_sse_apply_shifted(sofft_plan* plan, int32_t op, const void* v
  *   P^-1 = F^-1 (X_x (x) X_y)^T (lambda_x + lambda_y - E)^-1 (X_x (x) X_y) F,
  * with X and lambda of each axis as sofft_band_tables describes (built on the
  * first call and kept by the plan).  Arguments, workspace, blocking and status
- * as sofft_sse_solve; SOFFT_EUNSUPPORTED if a band's eigen-decomposition fails. */
+ * as sofft_sse_solve; 2D plans only; SOFFT_EUNSUPPORTED on a 3D plan or if a
+ * band's eigen-decomposition fails. */
 sofft_status sofft_sse_solve_banded(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
                                     int32_t nE, double field, void* x_out, double rtol, int32_t maxit,
                                     sofft_solve_stats* stats, void* stream);
@@ -430,7 +436,8 @@ sofft_status sofft_lp_train(sofft_lp* lp, sofft_plan* plan, const void* r, const
 /* sofft_sse_solve with the corrected preconditioner in flexible COCG
  * (beta = r_{k+1}^T (z_{k+1} - z_k) / rho_k).  An energy whose recurrence
  * residual has not reached a new minimum for `patience` iterations continues
- * with the plain preconditioner from its true residual (stats.fell_back = 1). */
+ * with the plain preconditioner from its true residual (stats.fell_back = 1).
+ * 2D plans only (SOFFT_EUNSUPPORTED on a 3D plan). */
 sofft_status sofft_sse_solve_learned(sofft_plan* plan, sofft_lp* lp, const void* f, int32_t f_per_energy,
                                      const double* E_host, int32_t nE, double field, void* x_out, double rtol,
                                      int32_t maxit, int32_t patience, sofft_solve_stats* stats, void* stream);
@@ -440,10 +447,11 @@ typedef enum {
   SOFFT_KERNEL_ROW = 0,   /* 2D row pass (x lines) of the propagation */
   SOFFT_KERNEL_COL = 1,   /* 2D column pass (y lines) of the propagation */
   SOFFT_KERNEL_1D = 2,    /* 1D whole-propagation kernel */
-  SOFFT_KERNEL_SSE_ROW_MV = 3,    /* stationary solver: p update + row part of A p */
-  SOFFT_KERNEL_SSE_COL_MV = 4,    /* column part of A p and p^T A p */
+  /* stationary solver; on 3D plans each kind times its group of line passes */
+  SOFFT_KERNEL_SSE_ROW_MV = 3,    /* p update + row part of A p (3D: x and y parts) */
+  SOFFT_KERNEL_SSE_COL_MV = 4,    /* column part of A p and p^T A p (3D: z part) */
   SOFFT_KERNEL_SSE_ROW_UPD = 5,   /* x, r update, ||r||^2, forward row FFT of r */
-  SOFFT_KERNEL_SSE_COL_PREC = 6,  /* column FFT, divide by k^2/2 - E, inverse */
+  SOFFT_KERNEL_SSE_COL_PREC = 6,  /* column FFT, divide by k^2/2 - E, inverse (3D: y, z, y) */
   SOFFT_KERNEL_SSE_ROW_PREC = 7,  /* inverse row FFT to z and r^T z */
   SOFFT_KERNEL_3D_KINETIC = 8,    /* 3D kinetic pass along one axis (with the potential factors) */
   SOFFT_KERNEL_3D_STRIP = 9,      /* 3D Crank-Nicolson on the ECS strip of one axis */

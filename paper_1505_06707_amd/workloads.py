@@ -27,6 +27,9 @@ Workloads (all atomic units):
   -1/sqrt(x^2 + y^2 + z^2 + 0.64), the same pulse along x, SECS on all six
   faces from 80% of the half-width, end angle 0.5; Gaussian with a seeded
   centre in [-2, 2]^3 and momentum in [-0.5, 0.5]^3; dt = 0.05.
+* ``sse_3d``   -- stationary equation on 128^3, h = 0.4 (box +-25.6), the static
+  part of the 3D potential and contour, the ``sse_2d`` source recipe on three
+  axes, 16 energies uniform in [0.05, 2.0], residual 1e-8.
 """
 from dataclasses import dataclass, field
 
@@ -135,10 +138,37 @@ class TDSE3D:
         return self.R0_frac * self.L / 2
 
 
+@dataclass(frozen=True)
+class SSE3D:
+    n: int = 128
+    h: float = 0.4
+    theta: float = 0.5
+    charge: float = 1.0
+    a2: float = 0.64
+    R0_frac: float = 0.8
+    n_energies: int = 16
+    E_lo: float = 0.05
+    E_hi: float = 2.0
+    rtol: float = 1e-8
+    sigma_cells: float = 2.0
+
+    @property
+    def L(self):
+        return self.n * self.h
+
+    @property
+    def R0(self):
+        return self.R0_frac * self.L / 2
+
+    def energies(self):
+        return np.linspace(self.E_lo, self.E_hi, self.n_energies)
+
+
 TDSE_1D = TDSE1D()
 TDSE_3D = TDSE3D()
 TDSE_2D = TDSE2D()
 SSE_2D = SSE2D()
+SSE_3D = SSE3D()
 LEARNED_2D = SSE2D(n=1024, n_energies=64)
 BATCH_SIZES = (256, 384, 512, 768, 1024)
 
@@ -212,3 +242,19 @@ def gaussian_3d(x, y, z, x0=0.0, y0=0.0, z0=0.0, px=0.0, py=0.0, pz=0.0):
     Z = np.asarray(z, dtype=float)[:, None, None]
     return (np.pi ** -0.75 * np.exp(-((X - x0) ** 2 + (Y - y0) ** 2 + (Z - z0) ** 2) / 2
                                     + 1j * (px * X + py * Y + pz * Z)))
+
+
+def smooth_source_3d(nz, ny, nx, seed, sigma_cells=2.0):
+    """The ``smooth_source`` recipe on a [nz][ny][nx] grid: complex white noise
+    smoothed by a periodic Gaussian of ``sigma_cells`` cells along every axis,
+    unit 2-norm."""
+    rng = np.random.default_rng(seed)
+    w = rng.normal(size=(nz, ny, nx)) + 1j * rng.normal(size=(nz, ny, nx))
+    filt = 1.0
+    for a, n in enumerate((nz, ny, nx)):
+        k = 2 * np.pi * np.fft.fftfreq(n)
+        shape = [1, 1, 1]
+        shape[a] = n
+        filt = filt * np.exp(-(sigma_cells * k) ** 2 / 2).reshape(shape)
+    s = np.fft.ifftn(np.fft.fftn(w) * filt)
+    return s / np.linalg.norm(s)

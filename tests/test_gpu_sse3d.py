@@ -87,18 +87,8 @@ def test_solve_matches_dense_gaussian_elimination_3d():
 
 
 def _source_3d(shape, seed):
-    """Smooth seeded source: complex white noise filtered by a periodic Gaussian
-    of sigma = 2 cells, unit 2-norm (the 2D recipe on three axes)."""
-    rng = np.random.default_rng(seed)
-    sh = tuple(reversed(shape))
-    w = rng.normal(size=sh) + 1j * rng.normal(size=sh)
-    filt = 1.0
-    for a, n in enumerate(sh):
-        k = 2 * np.pi * np.fft.fftfreq(n)
-        g = np.exp(-(2.0 * k) ** 2 / 2)
-        filt = filt * g.reshape([-1 if b == a else 1 for b in range(3)])
-    s = np.fft.ifftn(np.fft.fftn(w) * filt)
-    return s / np.linalg.norm(s)
+    nx, ny, nz = shape
+    return wl.smooth_source_3d(nz, ny, nx, seed)
 
 
 @pytest.mark.parametrize("shape,kind", [((32, 32, 32), "secs"), ((64, 32, 32), "tfecs"),
