@@ -17,7 +17,13 @@ COCG-valid variant of a local, pair-trained correction can do better:
   (7 x 7 on the inputs r and P^-1 r), used where it cannot break COCG, as the
   initial iterate, leaves a larger residual than x0 = 0 and saves nothing;
 * a diagonal rescaling by the contour, D P^-1 D with D = q(x) q(y), does not
-  help either.
+  help either;
+* the best position-dependent, complex-symmetric local correction
+  M^-1 = P^-1 + S (a 3 x 3 stencil whose weights are linear in the features
+  1, U, U^2 and the contour factors q^-2: the linear family a symmetric
+  G^T G-type correction with position features lies in), fitted by least
+  squares to PCG's pairs, predicts about 1% of e - P^-1 r and makes COCG
+  diverge.
 """
 import numpy as np
 import pytest
@@ -147,3 +153,45 @@ def test_rescaling_by_the_contour_does_not_help():
     P = op.precond
     op.precond = lambda v: D * P(D * v)
     assert _cocg_from(op, f, np.zeros_like(f)) >= plain
+
+
+def test_the_best_symmetric_position_dependent_local_correction_explains_nothing():
+    """S = sum_d (D_d T_d + T_-d D_d), (T_d v)(x) = v(x + d), d over the half
+    of a 3 x 3 stencil, D_d = sum_j c_dj phi_j with phi = 1, U, U^2,
+    q_x^-2 + q_y^-2, (q_x^-2 - 1)(q_y^-2 - 1): complex symmetric for every c,
+    so COCG accepts P^-1 + S.  The least-squares c over PCG's (r_k, e_k) pairs
+    of four training sources leaves >= 95% of e - P^-1 r unexplained, and
+    COCG with P^-1 + S needs more iterations than with P^-1 on a held-out
+    source."""
+    E = 0.7
+    ax, op = _problem(E)
+    V = op.V
+    iq = 1 / ax.q ** 2
+    feats = [np.ones((N, N), complex), V, V ** 2, iq[None, :] + iq[:, None], (iq[None, :] - 1) * (iq[:, None] - 1)]
+    offs = [(dy, dx) for dy in range(-1, 2) for dx in range(-1, 2) if (dy, dx) >= (0, 0)]
+    T = lambda v, d: np.roll(v, (-d[0], -d[1]), axis=(0, 1))
+
+    def columns(v):
+        cols = []
+        for d in offs:
+            for ph in feats:
+                cols.append(2 * ph * v if d == (0, 0) else ph * T(v, d) + T(ph * v, (-d[0], -d[1])))
+        return np.stack([c.ravel() for c in cols], axis=1)
+
+    X, Y = [], []
+    for seed in (101, 102, 103, 104):
+        for r, e in _pairs(op, -wl.smooth_source(N, N, seed=seed)):
+            X.append(columns(r))
+            Y.append((e - op.precond(r)).ravel())
+    X, Y = np.concatenate(X), np.concatenate(Y)
+    coef, *_ = np.linalg.lstsq(X, Y, rcond=None)
+    assert np.linalg.norm(X @ coef - Y) / np.linalg.norm(Y) > 0.95
+    S = lambda v: (columns(v) @ coef).reshape(N, N)
+    rng = np.random.default_rng(0)
+    u, w = (rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N)) for _ in range(2))
+    assert abs(np.sum(u * S(w)) - np.sum(w * S(u))) <= 1e-12 * abs(np.sum(u * S(w)))   # S = S^T
+    f = -wl.smooth_source(N, N, seed=0)
+    plain = _cocg_from(op, f, np.zeros_like(f))
+    P = op.precond
+    op.precond = lambda v: P(v) + S(v)
+    assert _cocg_from(op, f, np.zeros_like(f), maxit=3 * plain) > plain
