@@ -132,10 +132,11 @@ __device__ __forceinline__ void stage_twiddle_load(cx<double> (&w)[Shape<N>::P /
 
 // One rolled stage of radix RR with stride ns = R0 << sh (sh = log2(RR) (s-1));
 // w holds this stage's twiddles (stage_twiddle_load).
-template <typename X, int N, int SIGN, bool LAST>
+// XM: the write of element e goes to e ^ xm (the swizzled exchanges of fft2).
+template <typename X, int N, int SIGN, bool LAST, bool XM = false>
 __device__ __forceinline__ void rolled_stage(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, int t,
                                              const cx<double> (&w)[Shape<N>::P / Shape<N>::RR][Shape<N>::RR - 1],
-                                             int sh) {
+                                             int sh, int xm = 0) {
   constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, TPL = N / P, B = P / RR;
   constexpr int PAD = Shape<N>::PAD;
   const int ns = R0 << sh;
@@ -156,7 +157,12 @@ __device__ __forceinline__ void rolled_stage(cx<double> (&v)[Shape<N>::P], const
     } else {
       const int o = q * RR * ns + k;
 #pragma unroll
-      for (int m = 0; m < RR; ++m) L.template padded<PAD>(o + m * ns) = narrow<X>(a[m]);
+      for (int m = 0; m < RR; ++m) {
+        if constexpr (XM)
+          L[(o + m * ns) ^ xm] = narrow<X>(a[m]);
+        else
+          L.template padded<PAD>(o + m * ns) = narrow<X>(a[m]);
+      }
     }
   }
 }
@@ -222,12 +228,24 @@ __device__ __forceinline__ void fft(cx<double> (&v)[Shape<N>::P], const LineLDS<
 // a buffer is written again only two exchanges later, after a barrier every
 // thread passed once done reading it, so the barrier that follows each read
 // is dropped; one barrier at the end leaves both buffers free for the caller.
-template <typename X, int N, int SIGN, bool WAVE = false>
+//
+// SWZ (lines contiguous in LDS, radix-4 shapes with R0 = 4 and at least 64
+// threads per line): the first two exchanges store element e at
+// e ^ 5 ((e >> 4) & 3).  Their writes go to 4t + m (stage 0) and
+// 16 (t >> 2) + (t & 3) + 4m (first rolled stage), which put the 16 lanes of
+// a group on 4 of the 16 bank slots of 16 bytes; swizzled they cover all 16,
+// and the reads at t + TPL s stay conflict-free (the swizzle permutes within
+// aligned groups of 16 elements).  Both masks depend on t alone: (e >> 4) & 3
+// is (t >> 2) & 3 for those writes and (t >> 4) & 3 for the reads.
+template <typename X, int N, int SIGN, bool WAVE = false, bool SWZ = false>
 __device__ __forceinline__ void fft2(cx<double> (&v)[Shape<N>::P], const LineLDS<X>& L, const LineLDS<X>& Lb,
                                      int t, const cx<double>* __restrict__ tw) {
   constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, K = Shape<N>::K;
   constexpr int TPL = N / P, PAD = Shape<N>::PAD;
   constexpr int LR = RR == 4 ? 2 : (RR == 8 ? 3 : 4);
+  static_assert(!SWZ || (P == 4 && R0 == 4 && RR == 4 && PAD == 0 && TPL >= 64 && K >= 2), "swizzle shape");
+  const int xw = SWZ ? ((t >> 2) & 3) * 5 : 0;
+  const int tr = SWZ ? (t ^ (((t >> 4) & 3) * 5)) : t;
   cx<double> w[P / RR][RR - 1];
   stage_twiddle_load<N>(w, tw, t, 0);
   {
@@ -240,16 +258,37 @@ __device__ __forceinline__ void fft2(cx<double> (&v)[Shape<N>::P], const LineLDS
       for (int m = 0; m < R0; ++m) a[m] = v[b + m * B];
       DFT<R0, SIGN, double>::run(a);
 #pragma unroll
-      for (int m = 0; m < R0; ++m) L.template padded<PAD>(j * R0 + m) = narrow<X>(a[m]);
+      for (int m = 0; m < R0; ++m) {
+        if constexpr (SWZ)
+          L[(j * R0 + m) ^ xw] = narrow<X>(a[m]);
+        else
+          L.template padded<PAD>(j * R0 + m) = narrow<X>(a[m]);
+      }
     }
     line_sync<WAVE>();
 #pragma unroll
-    for (int s = 0; s < P; ++s) v[s] = widen(L.template padded<PAD>(t + TPL * s));
+    for (int s = 0; s < P; ++s) {
+      if constexpr (SWZ)
+        v[s] = widen(L[tr + TPL * s]);
+      else
+        v[s] = widen(L.template padded<PAD>(t + TPL * s));
+    }
   }
   int off = 0;
   bool odd = true;
+  int sh0 = 0;
+  if constexpr (SWZ) {   // the first rolled stage (stride R0), swizzled
+    rolled_stage<X, N, SIGN, false, true>(v, Lb, t, w, 0, xw);
+    off += (RR - 1) * R0;
+    stage_twiddle_load<N>(w, tw + off, t, LR);
+    line_sync<WAVE>();
+#pragma unroll
+    for (int s = 0; s < P; ++s) v[s] = widen(Lb[tr + TPL * s]);
+    odd = false;
+    sh0 = LR;
+  }
 #pragma unroll 1
-  for (int sh = 0; sh < LR * (K - 1); sh += LR) {
+  for (int sh = sh0; sh < LR * (K - 1); sh += LR) {
     const LineLDS<X>& Lx = odd ? Lb : L;
     rolled_stage<X, N, SIGN, false>(v, Lx, t, w, sh);
     off += (RR - 1) * (R0 << sh);
@@ -261,6 +300,13 @@ __device__ __forceinline__ void fft2(cx<double> (&v)[Shape<N>::P], const LineLDS
   }
   rolled_stage<X, N, SIGN, true>(v, L, t, w, LR * (K - 1));
   line_sync<WAVE>();
+}
+
+// Whether fft2 may swizzle a line of N points held contiguously in LDS.
+template <int N>
+constexpr bool fft2_swizzle() {
+  return Shape<N>::P == 4 && Shape<N>::R0 == 4 && Shape<N>::RR == 4 && Shape<N>::PAD == 0 && N / 4 >= 64 &&
+         Shape<N>::K >= 2;
 }
 
 // Copy the stage twiddle tables (N entries) from global memory to LDS (all

@@ -57,6 +57,7 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
   const size_t o = idx3(lx, ly, lz, a.nx, a.ny);   // line origin within one vector
   const size_t off = size_t(e) * a.vec + o;
   constexpr bool wave = AXIS == 0 && TPL <= 64 && 64 % TPL == 0;
+  constexpr bool swz = AXIS == 0 && fft2_swizzle<N>();   // x lines are contiguous in LDS
   const LineLDS<double> L = AXIS == 0 ? LineLDS<double>{lds, c * 2 * E, 1} : LineLDS<double>{lds, c, LPB};
   const LineLDS<double> Lb =
       AXIS == 0 ? LineLDS<double>{lds, c * 2 * E + E, 1} : LineLDS<double>{lds, c + E * LPB, LPB};
@@ -108,13 +109,13 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
       for (int s = 0; s < P; ++s) pv[s] = v[s];
     }
     // T_a v = F_a^-1 (k_a^2/2) F_a v
-    fft2<double, N, -1, wave>(v, L, Lb, t, tw);
+    fft2<double, N, -1, wave, swz>(v, L, Lb, t, tw);
 #pragma unroll
     for (int s = 0; s < P; ++s) {
       const double k = kval(t + TPL * s, N, La);
       v[s] = (0.5 * k * k / N) * v[s];
     }
-    fft2<double, N, +1, wave>(v, L, Lb, t, tw);
+    fft2<double, N, +1, wave, swz>(v, L, Lb, t, tw);
     cx<double> dot = zero;
     if (live) {
 #pragma unroll
@@ -161,7 +162,7 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
       }
       v[s] = rv;
     }
-    fft2<double, N, -1, wave>(v, L, Lb, t, tw);
+    fft2<double, N, -1, wave, swz>(v, L, Lb, t, tw);
     if (live) {
 #pragma unroll
       for (int s = 0; s < P; ++s) a.s[off + t + TPL * s] = v[s];
@@ -173,11 +174,11 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = a.s[off + size_t(t + TPL * s) * ld];
     if constexpr (OP == kFwdY) {
-      fft2<double, N, -1, wave>(v, L, Lb, t, tw);
+      fft2<double, N, -1, wave, swz>(v, L, Lb, t, tw);
     } else if constexpr (OP == kInvY) {
-      fft2<double, N, +1, wave>(v, L, Lb, t, tw);
+      fft2<double, N, +1, wave, swz>(v, L, Lb, t, tw);
     } else {
-      fft2<double, N, -1, wave>(v, L, Lb, t, tw);
+      fft2<double, N, -1, wave, swz>(v, L, Lb, t, tw);
       const double kx = kval(lx, a.nx, a.Lx), ky = kval(ly, a.ny, a.Ly), En = a.E[e];
       const double kxy = kx * kx + ky * ky;
       const double eta = a.eta ? a.eta[e] : 0.0;
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
           v[s] = cmul(v[s], cx<double>{q * d, q * eta});
         }
       }
-      fft2<double, N, +1, wave>(v, L, Lb, t, tw);
+      fft2<double, N, +1, wave, swz>(v, L, Lb, t, tw);
     }
     if (live) {
 #pragma unroll
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
       v[s] = a.s[off + t + TPL * s];
       rv[s] = a.r[off + t + TPL * s];
     }
-    fft2<double, N, +1, wave>(v, L, Lb, t, tw);
+    fft2<double, N, +1, wave, swz>(v, L, Lb, t, tw);
     cx<double> dot = zero;
     if (live) {
 #pragma unroll

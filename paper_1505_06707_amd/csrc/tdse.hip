@@ -265,11 +265,12 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     constexpr bool wave_rows = TPL <= 64 && 64 % TPL == 0;
     if constexpr (fft_buffers<N, X>() == 2) {
       const LineLDS<X> Lb{lines, l * a.lds_line + fft_lds_elems<N>(), 1};
-      fft2<X, N, -1, wave_rows>(v, L, Lb, t, a.tw);
+      constexpr bool swz = fft2_swizzle<N>();   // rows are contiguous in LDS
+      fft2<X, N, -1, wave_rows, swz>(v, L, Lb, t, a.tw);
       if constexpr (!early) load_kin();
 #pragma unroll
       for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
-      fft2<X, N, +1, wave_rows>(v, L, Lb, t, a.tw);
+      fft2<X, N, +1, wave_rows, swz>(v, L, Lb, t, a.tw);
     } else {
       fft<X, N, -1, wave_rows>(v, L, t, a.tw);
       if constexpr (!early) load_kin();

@@ -94,10 +94,11 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_kinetic(Pass3<T> a) {
   constexpr bool wave = AXIS == 0 && TPL <= 64 && 64 % TPL == 0;
   const LineLDS<double> L = AXIS == 0 ? LineLDS<double>{lds, c * 2 * E, 1} : LineLDS<double>{lds, c, LPB};
   const LineLDS<double> Lb = AXIS == 0 ? LineLDS<double>{lds, c * 2 * E + E, 1} : LineLDS<double>{lds, c + E * LPB, LPB};
-  fft2<double, N, -1, wave>(v, L, Lb, t, a.tw);
+  constexpr bool swz = AXIS == 0 && fft2_swizzle<N>();   // x lines are contiguous in LDS
+  fft2<double, N, -1, wave, swz>(v, L, Lb, t, a.tw);
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
-  fft2<double, N, +1, wave>(v, L, Lb, t, a.tw);
+  fft2<double, N, +1, wave, swz>(v, L, Lb, t, a.tw);
   if (a.post_step >= 0) {
     const double f = a.f_mid ? a.f_mid[a.post_step] : 0.0;
 #pragma unroll
