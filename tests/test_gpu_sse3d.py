@@ -175,3 +175,26 @@ def test_per_energy_sources_and_rejections_3d():
     with pytest.raises(sofft.SofftError):
         plan.sse_solve(torch.from_numpy(f[0]).cuda(), Es, banded=True)   # the banded form is 2D only
     plan.close()
+
+
+def test_full_3d_workload_sampled():
+    """The 3D stationary workload as the benchmark runs it (128^3, h = 0.4,
+    16 energies in [0.05, 2.0], rtol 1e-8, one launch set): every energy
+    converges, and the oracle's true residual of the lowest and highest energy
+    is within rtol."""
+    from paper_1505_06707_amd import sofft
+    c = wl.SSE_3D
+    print(f"sse3d workload {c.n}^3 x {c.n_energies}", flush=True)
+    plan = sofft.Plan([c.n] * 3, [c.L] * 3, R0=[c.R0] * 3, theta=c.theta, charge=c.charge, a2=c.a2)
+    f = -wl.smooth_source_3d(c.n, c.n, c.n, seed=0)
+    E = c.energies()
+    x, st, code = plan.sse_solve(torch.from_numpy(f).cuda(), E, rtol=c.rtol)
+    assert code == 0 and all(q["status"] == 0 for q in st)
+    ax = ot.Axis(c.n, c.L, R0=c.R0, theta=c.theta)
+    V = ot.softcore(c.charge, c.a2, ax.z[None, None, :], ax.z[None, :, None], ax.z[:, None, None])
+    for k in (0, len(E) - 1):
+        op = osse.Operator((ax, ax, ax), V, E[k])
+        res = float(np.linalg.norm(f - op.matvec(x[k].cpu().numpy())) / np.linalg.norm(f))
+        print(f"   E={E[k]:.3f}: {st[k]['iterations']} iterations, oracle true residual {res:.2e}", flush=True)
+        assert res <= c.rtol * (1 + 1e-3)
+    plan.close()
