@@ -8,7 +8,8 @@ is the Fourier-basis block of K_a = -1/2 d/dx q^-2 d/dx.  Its eigenvectors chi,
 normalised by chi^T chi = 1, are the rows of the block of X, and
     P^-1 = F^-1 X^T (Lambda - E)^-1 X F.
 In 2D the kinetic operator is K_x + K_y, so X = X_x (x) X_y and the divisor is
-lambda_x + lambda_y - E.
+lambda_x + lambda_y - E; in 3D (Sec. III's many-dimensional case, read the same
+way) X = X_x (x) X_y (x) X_z and the divisor lambda_x + lambda_y + lambda_z - E.
 
 Readings:
 * Q_{nm} depends on k_m - k_n only (Toeplitz).  It is evaluated by the grid
@@ -81,23 +82,23 @@ class AxisBands:
 
 
 def preconditioner(op, nbw=N_BW):
-    """P^-1 of Eq. PreconFFT_ECS for an ``oracle.sse.Operator`` (1D or 2D)."""
+    """P^-1 of Eq. PreconFFT_ECS for an ``oracle.sse.Operator`` (1D, 2D or 3D).
+    Axis a of the grid is array axis nd - 1 - a (x fastest)."""
     axes = op.axes
+    nd = len(axes)
     ab = [AxisBands(a, nbw) for a in axes]
-    if len(axes) == 1:
-        div = ab[0].lam - op.E
-    else:
-        div = ab[0].lam[None, :] + ab[1].lam[:, None] - op.E
+    div = -op.E
+    for a, bnd in enumerate(ab):
+        shape = [1] * nd
+        shape[nd - 1 - a] = bnd.n
+        div = div + bnd.lam.reshape(shape)
 
     def apply(r):
         s = op._F(r)
-        if len(axes) == 1:
-            s = ab[0].apply_X(s, 0)
-            s = s / div
-            s = ab[0].apply_X(s, 0, transpose=True)
-        else:
-            s = ab[0].apply_X(ab[1].apply_X(s, 0), 1)
-            s = s / div
-            s = ab[1].apply_X(ab[0].apply_X(s, 1, transpose=True), 0, transpose=True)
+        for a, bnd in enumerate(ab):
+            s = bnd.apply_X(s, nd - 1 - a)
+        s = s / div
+        for a, bnd in reversed(list(enumerate(ab))):
+            s = bnd.apply_X(s, nd - 1 - a, transpose=True)
         return op._Finv(s)
     return apply
