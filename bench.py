@@ -268,7 +268,7 @@ def gpu_pcg(sofft, wl, torch, n_energies=None, seed=0, extras=True, shifted=Fals
 def gpu_pcg3d(sofft, wl, torch, seed=0):
     """Batched COCG to 1e-8 on the 3D stationary workload (128^3, 16 energies):
     time to tolerance, iterations, the event-timed line-pass groups and their
-    algorithmic bytes."""
+    algorithmic bytes; then the same solve with the banded ECS preconditioner."""
     c = wl.SSE_3D
     plan = sofft.Plan([c.n] * 3, [c.L] * 3, R0=[c.R0] * 3, theta=c.theta, charge=c.charge, a2=c.a2)
     f = torch.from_numpy(-wl.smooth_source_3d(c.n, c.n, c.n, seed=seed)).cuda()
@@ -287,6 +287,7 @@ def gpu_pcg3d(sofft, wl, torch, seed=0):
              "x_precond_dot": sofft.KERNEL_SSE_ROW_PREC}
     kern = {k: plan.timing_read(v) for k, v in kinds.items()}
     plan.timing(False)
+    band = pcg_banded(plan, f, E, c.rtol, out, wall, torch)
     plan.close()
     its = np.array([s["iterations"] for s in stats])
     res = np.array([s["rel_residual"] for s in stats])
@@ -305,7 +306,7 @@ def gpu_pcg3d(sofft, wl, torch, seed=0):
             "max_true_rel_residual": float(res.max()),
             "us_per_energy_iteration": kern_s / total_it * 1e6,
             "kernel_time_s": kern_s, "achieved_GBs_all_passes": 26 * 16 * npts * total_it / kern_s / 1e9,
-            "group_GBs": gbs, "kernels_ms": {k: v[0] for k, v in kern.items()}}
+            "group_GBs": gbs, "kernels_ms": {k: v[0] for k, v in kern.items()}, "banded": band}
 
 
 def gpu_pcg_tfecs(sofft, wl, torch, n_energies=32, seed=0, shifted=False):
@@ -666,6 +667,9 @@ def main():
         log(f"  {pcg3d['time_to_tol_s']:.3f} s, iterations {pcg3d['iterations']['min']}.."
             f"{pcg3d['iterations']['max']}, {pcg3d['us_per_energy_iteration']:.0f} us per energy-iteration, "
             f"{pcg3d['achieved_GBs_all_passes']:.0f} GB/s over the passes")
+        bd = pcg3d["banded"]
+        log(f"  banded ECS preconditioner: {bd['time_to_tol_s']:.3f} s, iterations mean "
+            f"{bd['iterations']['mean']:.0f}, {bd['speedup_vs_plain']:.2f}x the plain solve")
 
     batch = None
     if not args.no_batch:

@@ -104,8 +104,8 @@ int32_t sofft_version(void);
  * 256 nodes per axis in 2D and 3D.  3D: the paper is 1D and names the
  * many-dimensional case as its next step; the step is read separably,
  * K = (k_x^2 + k_y^2 + k_z^2)/2 and e^{-iC dt} = CN(C_x) CN(C_y) CN(C_z).
- * The stationary solver takes 2D and 3D complex128 plans (its banded
- * preconditioner and learned correction 2D only); batches take 2D plans.
+ * The stationary solver takes 2D and 3D complex128 plans (its learned
+ * correction 2D only); batches take 2D plans.
  * Returns SOFFT_EINVAL / SOFFT_EUNSUPPORTED / SOFFT_ENOMEM / SOFFT_EHIP. */
 sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out);
 
@@ -260,10 +260,10 @@ sofft_status sofft_sse_apply_shifted(sofft_plan* plan, int32_t op, const void* v
 /* sofft_sse_solve with the banded ECS eigen-preconditioner of Sec. III,
  * Eq. PreconFFT_ECS, instead of Eq. PreconFFT: in 2D
  *   P^-1 = F^-1 (X_x (x) X_y)^T (lambda_x + lambda_y - E)^-1 (X_x (x) X_y) F,
+ * and in 3D with X = X_x (x) X_y (x) X_z and lambda_x + lambda_y + lambda_z - E,
  * with X and lambda of each axis as sofft_band_tables describes (built on the
  * first call and kept by the plan).  Arguments, workspace, blocking and status
- * as sofft_sse_solve; 2D plans only; SOFFT_EUNSUPPORTED on a 3D plan or if a
- * band's eigen-decomposition fails. */
+ * as sofft_sse_solve; SOFFT_EUNSUPPORTED if a band's eigen-decomposition fails. */
 sofft_status sofft_sse_solve_banded(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
                                     int32_t nE, double field, void* x_out, double rtol, int32_t maxit,
                                     sofft_solve_stats* stats, void* stream);

@@ -515,7 +515,7 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
       set_error("ECS strip of " + std::to_string(pl->ax[d].m) + " nodes exceeds half the axis; increase R0");
       st = SOFFT_EUNSUPPORTED;
     }
-    if (st == SOFFT_OK) st = upload_static(pl->ax[d], p.ndim == 2 && p.dtype == SOFFT_C128);
+    if (st == SOFFT_OK) st = upload_static(pl->ax[d], p.ndim >= 2 && p.dtype == SOFFT_C128);
     if (st != SOFFT_OK) {
       for (int e = 0; e < 3; ++e) free_axis(pl->ax[e]);
       delete pl;

@@ -179,41 +179,6 @@ __global__ void __launch_bounds__(sse_col_bound<N>()) k_sse_col_mv(SseArgs a, in
   }
 }
 
-// Block-diagonal multiply along a line in Fourier space (Eq. PreconFFT_ECS):
-// v[n] <- sum_{i < width[n]} coef[i * N + n] v[start[n] + i], the line held
-// as v[s] = element t + TPL s (natural FFT index order) and passed through the
-// LDS view L.  Every thread of the block calls it (block barriers).
-template <int N>
-__device__ __forceinline__ void band_apply(cx<double> (&v)[Shape<N>::P], const LineLDS<double>& L, int t,
-                                           const cx<double>* __restrict__ coef, const int* __restrict__ start,
-                                           const int* __restrict__ width) {
-  constexpr int P = Shape<N>::P, TPL = N / P;
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < P; ++s) L[t + TPL * s] = v[s];
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < P; ++s) {
-    const int n = t + TPL * s, st = start[n], w = width[n];
-    cx<double> acc{0.0, 0.0};
-    // four entries per round, loads issued together (w <= 19: at most 5 rounds)
-    for (int i0 = 0; i0 < w; i0 += 4) {
-      cx<double> c[4], x[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int i = min(i0 + j, w - 1);
-        c[j] = coef[size_t(i) * N + n];
-        x[j] = L[st + i];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (i0 + j < w) acc = cfma(acc, c[j], x[j]);
-    }
-    v[s] = acc;
-  }
-  __syncthreads();
-}
-
 // ---------------------------------------------------------------- K4: update and forward row FFT
 template <int N, bool BANDED>
 __global__ void __launch_bounds__(sse_row_bound<N>(), (sse_row_waves<N, BANDED>())) k_sse_row_upd(SseArgs a, int want, int mode) {
@@ -800,11 +765,11 @@ static sofft_status sse_check_plan(const Plan& p) {
   return SOFFT_OK;
 }
 
-// The tables of the banded preconditioner of both axes into the solver's arguments.
+// The tables of the banded preconditioner of every axis into the solver's arguments.
 static sofft_status use_bands(Plan& p, SseArgs& a) {
   sofft_status st;
-  if ((st = ensure_bands(p.ax[0])) != SOFFT_OK) return st;
-  if ((st = ensure_bands(p.ax[1])) != SOFFT_OK) return st;
+  for (int d = 0; d < p.prob.ndim; ++d)
+    if ((st = ensure_bands(p.ax[d])) != SOFFT_OK) return st;
   const Axis &ax = p.ax[0], &ay = p.ax[1];
   a.banded = 1;
   a.bx_lam = static_cast<const cx<double>*>(ax.band_lam.p);
@@ -817,6 +782,14 @@ static sofft_status use_bands(Plan& p, SseArgs& a) {
   a.by_xc = static_cast<const cx<double>*>(ay.band_xc.p);
   a.by_start = static_cast<const int*>(ay.band_start.p);
   a.by_width = static_cast<const int*>(ay.band_width.p);
+  if (p.prob.ndim == 3) {
+    const Axis& az = p.ax[2];
+    a.bz_lam = static_cast<const cx<double>*>(az.band_lam.p);
+    a.bz_xr = static_cast<const cx<double>*>(az.band_xr.p);
+    a.bz_xc = static_cast<const cx<double>*>(az.band_xc.p);
+    a.bz_start = static_cast<const int*>(az.band_start.p);
+    a.bz_width = static_cast<const int*>(az.band_width.p);
+  }
   return SOFFT_OK;
 }
 
@@ -825,8 +798,8 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
                        int patience, const double* eta_host, int banded) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
-  if (p.prob.ndim == 3 && (lp || banded)) {
-    set_error("the learned correction and the banded preconditioner work on 2D grids");
+  if (p.prob.ndim == 3 && lp) {
+    set_error("the learned correction works on 2D grids");
     return SOFFT_EUNSUPPORTED;
   }
   SseArgs a{};
@@ -981,10 +954,6 @@ sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double
                        int banded) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
-  if (p.prob.ndim == 3 && banded) {
-    set_error("the banded preconditioner works on 2D grids");
-    return SOFFT_EUNSUPPORTED;
-  }
   SseArgs a{};
   if ((st = sse_prepare(p, 1, field, a, s)) != SOFFT_OK) return st;
   SOFFT_HIP_TRY(hipMemcpyAsync(a.E_dev, &E, sizeof(double), hipMemcpyHostToDevice, s));

@@ -52,6 +52,11 @@ struct SseArgs {
   const cx<double>* by_xc;
   const int* by_start;
   const int* by_width;
+  const cx<double>* bz_lam;    // z axis (3D grids)
+  const cx<double>* bz_xr;
+  const cx<double>* bz_xc;
+  const int* bz_start;
+  const int* bz_width;
   CocgScalars* sc;             // [nE]
   double* part_rr;             // [nE][nblk_row]
   cx<double>* part_rz;         // [nE][nblk_row]
@@ -112,6 +117,41 @@ __device__ __forceinline__ cx<double> c_apply(const LineLDS<double>& L, int e, i
   if (p >= m) return {0.0, 0.0};
   const int em = e == 0 ? n - 1 : e - 1, ep = e + 1 == n ? 0 : e + 1;
   return cmul(cs[p], L[em]) + cmul(cs[m + p], L[e]) + cmul(cs[2 * m + p], L[ep]);
+}
+
+// Block-diagonal multiply along a line in Fourier space (Eq. PreconFFT_ECS):
+// v[n] <- sum_{i < width[n]} coef[i * N + n] v[start[n] + i], the line held
+// as v[s] = element t + TPL s (natural FFT index order) and passed through the
+// LDS view L.  Every thread of the block calls it (block barriers).
+template <int N>
+__device__ __forceinline__ void band_apply(cx<double> (&v)[Shape<N>::P], const LineLDS<double>& L, int t,
+                                           const cx<double>* __restrict__ coef, const int* __restrict__ start,
+                                           const int* __restrict__ width) {
+  constexpr int P = Shape<N>::P, TPL = N / P;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < P; ++s) L[t + TPL * s] = v[s];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int n = t + TPL * s, st = start[n], w = width[n];
+    cx<double> acc{0.0, 0.0};
+    // four entries per round, loads issued together (w <= 19: at most 5 rounds)
+    for (int i0 = 0; i0 < w; i0 += 4) {
+      cx<double> c[4], x[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = min(i0 + j, w - 1);
+        c[j] = coef[size_t(i) * N + n];
+        x[j] = L[st + i];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (i0 + j < w) acc = cfma(acc, c[j], x[j]);
+    }
+    v[s] = acc;
+  }
+  __syncthreads();
 }
 
 // The solver's passes, in the order of one COCG iteration (the 3D launcher

@@ -13,6 +13,10 @@
 //   K4   x: x += alpha p, r -= alpha w, partial ||r||^2, s = F_x r
 //   K5   y: s = F_y s;  z: s = F_z^-1 (F_z s / (K - E)) / (nx ny nz);  y: s = F_y^-1 s
 //   K6   x: z = F_x^-1 s, partial r^T z
+// With the banded ECS eigen-preconditioner (Eq. PreconFFT_ECS, X = X_x (x) X_y
+// (x) X_z) each forward transform is followed by the band multiply X_a of its
+// axis, the divisor is lambda_x + lambda_y + lambda_z - E, and each inverse
+// transform is preceded by X_a^T.
 // Partial sums are one per block; a reduction kernel adds each energy's in a
 // fixed order into its first slot, so the scalar steps read one value and the
 // result does not depend on scheduling.
@@ -31,7 +35,7 @@ constexpr int op_axis() {
   return (OP == kMvX || OP == kUpdX || OP == kPrecX) ? 0 : ((OP == kMvZ || OP == kDivZ) ? 2 : 1);
 }
 
-template <int N, int OP>
+template <int N, int OP, bool BANDED = false>
 __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, int mode) {
   constexpr int AXIS = op_axis<OP>();
   constexpr int P = Shape<N>::P, TPL = N / P, LPB = k3_lines<N>(), E = fft_lds_elems<N>();
@@ -163,6 +167,7 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
       v[s] = rv;
     }
     fft2<double, N, -1, wave, swz>(v, L, Lb, t, tw);
+    if constexpr (BANDED) band_apply<N>(v, L, t, a.bx_xr, a.bx_start, a.bx_width);   // X_x
     if (live) {
 #pragma unroll
       for (int s = 0; s < P; ++s) a.s[off + t + TPL * s] = v[s];
@@ -175,7 +180,9 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
     for (int s = 0; s < P; ++s) v[s] = a.s[off + size_t(t + TPL * s) * ld];
     if constexpr (OP == kFwdY) {
       fft2<double, N, -1, wave, swz>(v, L, Lb, t, tw);
+      if constexpr (BANDED) band_apply<N>(v, L, t, a.by_xr, a.by_start, a.by_width);   // X_y
     } else if constexpr (OP == kInvY) {
+      if constexpr (BANDED) band_apply<N>(v, L, t, a.by_xc, a.by_start, a.by_width);   // X_y^T
       fft2<double, N, +1, wave, swz>(v, L, Lb, t, tw);
     } else {
       fft2<double, N, -1, wave, swz>(v, L, Lb, t, tw);
@@ -183,7 +190,18 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
       const double kxy = kx * kx + ky * ky;
       const double eta = a.eta ? a.eta[e] : 0.0;
       const double scale = 1.0 / (double(a.nx) * double(a.ny) * double(N));
-      if (eta == 0.0) {
+      if constexpr (BANDED) {
+        // X_z, then 1/(lambda_x + lambda_y + lambda_z - E), then X_z^T
+        band_apply<N>(v, L, t, a.bz_xr, a.bz_start, a.bz_width);
+        const cx<double> lxy = a.bx_lam[lx] + a.by_lam[ly] - cx<double>{En, 0.0};
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+          const cx<double> dd = lxy + a.bz_lam[t + TPL * s];
+          const double q = scale / (dd.re * dd.re + dd.im * dd.im);
+          v[s] = cmul(v[s], cx<double>{q * dd.re, -q * dd.im});
+        }
+        band_apply<N>(v, L, t, a.bz_xc, a.bz_start, a.bz_width);
+      } else if (eta == 0.0) {
 #pragma unroll
         for (int s = 0; s < P; ++s) {
           const double kz = kval(t + TPL * s, N, a.Lz);
@@ -214,6 +232,7 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
       v[s] = a.s[off + t + TPL * s];
       rv[s] = a.r[off + t + TPL * s];
     }
+    if constexpr (BANDED) band_apply<N>(v, L, t, a.bx_xc, a.bx_start, a.bx_width);   // X_x^T
     fft2<double, N, +1, wave, swz>(v, L, Lb, t, tw);
     cx<double> dot = zero;
     if (live) {
@@ -251,26 +270,38 @@ __global__ void __launch_bounds__(kReduceThreads) k3_reduce(V* part, int stride,
   if (threadIdx.x == 0) put(q[0], sum);
 }
 
-template <int N, int OP>
+template <int N, int OP, bool BANDED>
 sofft_status pass_n(const SseArgs& a, int want, int mode, hipStream_t s) {
   constexpr int AXIS = op_axis<OP>(), LPB = k3_lines<N>();
   const size_t lds = size_t(LPB) * 2 * fft_lds_elems<N>() * sizeof(cx<double>);
   if (lds > 65536) {
-    sofft_status st = raise_lds_limit(reinterpret_cast<const void*>(k3_sse<N, OP>), 150 * 1024);
+    sofft_status st = raise_lds_limit(reinterpret_cast<const void*>(k3_sse<N, OP, BANDED>), 150 * 1024);
     if (st != SOFFT_OK) return st;
   }
   const int nlines = AXIS == 0 ? a.ny * a.nz : (AXIS == 1 ? a.nx * a.nz : a.nx * a.ny);
   const dim3 grid((nlines + LPB - 1) / LPB, a.nE);
-  k3_sse<N, OP><<<grid, k3_threads<N>(), lds, s>>>(a, want, mode);
+  k3_sse<N, OP, BANDED><<<grid, k3_threads<N>(), lds, s>>>(a, want, mode);
   SOFFT_HIP_TRY(hipGetLastError());
   return SOFFT_OK;
 }
+
+// The preconditioner's passes have banded instantiations (a.banded); the
+// matrix passes do not need them.
+template <int OP>
+constexpr bool has_banded() { return OP == kUpdX || OP == kFwdY || OP == kDivZ || OP == kInvY || OP == kPrecX; }
 
 template <int OP>
 sofft_status pass(const SseArgs& a, int want, int mode, hipStream_t s) {
   constexpr int AXIS = op_axis<OP>();
   const int n = AXIS == 0 ? a.nx : (AXIS == 1 ? a.ny : a.nz);
-  SOFFT_3D_SWITCH(n, (pass_n<N_, OP>(a, want, mode, s)))
+  if constexpr (has_banded<OP>()) {
+    if (a.banded) {
+      SOFFT_3D_SWITCH(n, (pass_n<N_, OP, true>(a, want, mode, s)))
+      set_error("unsupported 3D line length");
+      return SOFFT_EUNSUPPORTED;
+    }
+  }
+  SOFFT_3D_SWITCH(n, (pass_n<N_, OP, false>(a, want, mode, s)))
   set_error("unsupported 3D line length");
   return SOFFT_EUNSUPPORTED;
 }
