@@ -104,7 +104,7 @@ int32_t sofft_version(void);
  * 256 nodes per axis in 2D and 3D.  3D: the paper is 1D and names the
  * many-dimensional case as its next step; the step is read separably,
  * K = (k_x^2 + k_y^2 + k_z^2)/2 and e^{-iC dt} = CN(C_x) CN(C_y) CN(C_z).
- * The stationary solver takes 2D and 3D complex128 plans (its learned
+ * The stationary solver takes complex128 plans of any dimension (its learned
  * correction 2D only); batches take 2D plans.
  * Returns SOFFT_EINVAL / SOFFT_EUNSUPPORTED / SOFFT_ENOMEM / SOFFT_EHIP. */
 sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out);
@@ -115,7 +115,7 @@ sofft_status sofft_plan_destroy(sofft_plan* plan);
 
 /* Bytes of device workspace the plan needs for sofft_propagate, sofft_norm2
  * and, with n_energies > 0, for stationary solves and applications of up to
- * n_energies energies at once (2D and 3D complex128 plans; SOFFT_EUNSUPPORTED
+ * n_energies energies at once (complex128 plans; SOFFT_EUNSUPPORTED
  * otherwise).  About 16 bytes per grid point for propagation (the table of
  * exp(-i V0 dt/2), room for a caller's V0), plus about (5 n_energies + 1) 16
  * bytes per grid point for solves.  Host only: nothing is enqueued. */
@@ -220,9 +220,12 @@ typedef struct {
  *   E_host  host, nE energies
  *   x_out   device, [nE][n_y][n_x] ([nE][n_z][n_y][n_x] in 3D), written
  *   stats   host, nE entries (may be NULL)
- * 2D and 3D complex128 plans.  In 3D (Sec. III: the FFT preconditioner carries
- * over to the many-dimensional case) K = (k_x^2 + k_y^2 + k_z^2)/2,
- * C = C_x + C_y + C_z and P^-1 uses the full 3D transform.  The bound
+ * Complex128 plans of 1, 2 or 3 dimensions.  In 3D (Sec. III: the FFT
+ * preconditioner carries over to the many-dimensional case)
+ * K = (k_x^2 + k_y^2 + k_z^2)/2, C = C_x + C_y + C_z and P^-1 uses the full 3D
+ * transform.  In 1D (the setting of the paper's example, Sec. V) every energy
+ * is one workgroup that runs the whole iteration on chip: the call is one
+ * launch, and its stats and x are final when it returns.  The bound
  * workspace must hold sofft_workspace_size(plan, nE) bytes (about
  * (5 nE + 1) 16 bytes per grid point).
  * Blocking: returns after the solve.  Returns SOFFT_OK when every energy met
@@ -455,6 +458,7 @@ typedef enum {
   SOFFT_KERNEL_SSE_ROW_PREC = 7,  /* inverse row FFT to z and r^T z */
   SOFFT_KERNEL_3D_KINETIC = 8,    /* 3D kinetic pass along one axis (with the potential factors) */
   SOFFT_KERNEL_3D_STRIP = 9,      /* 3D Crank-Nicolson on the ECS strip of one axis */
+  SOFFT_KERNEL_SSE_1D = 10,       /* 1D stationary solve or application (one workgroup per energy) */
   SOFFT_KERNEL_COUNT_ = 16
 } sofft_kernel;
 

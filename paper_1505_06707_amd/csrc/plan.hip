@@ -515,7 +515,7 @@ sofft_status sofft_plan_create(const sofft_problem* prob, sofft_plan** out) {
       set_error("ECS strip of " + std::to_string(pl->ax[d].m) + " nodes exceeds half the axis; increase R0");
       st = SOFFT_EUNSUPPORTED;
     }
-    if (st == SOFFT_OK) st = upload_static(pl->ax[d], p.ndim >= 2 && p.dtype == SOFFT_C128);
+    if (st == SOFFT_OK) st = upload_static(pl->ax[d], p.dtype == SOFFT_C128);
     if (st != SOFFT_OK) {
       for (int e = 0; e < 3; ++e) free_axis(pl->ax[e]);
       delete pl;
@@ -538,8 +538,8 @@ sofft_status sofft_workspace_size(const sofft_plan* plan, int32_t n_energies, in
     set_error("bad argument to sofft_workspace_size");
     return SOFFT_EINVAL;
   }
-  if (n_energies > 0 && (plan->prob.ndim < 2 || plan->prob.dtype != SOFFT_C128)) {
-    set_error("the stationary solver works on 2D and 3D complex128 plans");
+  if (n_energies > 0 && plan->prob.dtype != SOFFT_C128) {
+    set_error("the stationary solver works on complex128 plans");
     return SOFFT_EUNSUPPORTED;
   }
   *bytes = int64_t(plan_ws_layout(*plan, n_energies).total);

@@ -357,13 +357,6 @@ __global__ void __launch_bounds__(256) k_sse_lp_dot(SseArgs a) {
 }
 
 // ---------------------------------------------------------------- scalar steps (one thread per energy)
-__device__ __forceinline__ double cabs2(cx<double> v) { return v.re * v.re + v.im * v.im; }
-
-__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
-  const double d = b.re * b.re + b.im * b.im;
-  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
-}
-
 // After the initial r = f, z = P^-1 r: ||f||^2, rho = r^T z.
 __global__ void k_sse_init(SseArgs a) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -407,12 +400,6 @@ __global__ void k_sse_alpha(SseArgs a) {
   sc.first = 0;
 }
 
-// Plain COCG restarts from the true residual after this many iterations
-// without a new minimum of ||r||.  On the 512^2 TFECS workload (2000-6300
-// iterations per energy) single energies otherwise stalled near 1e-6..1e-5;
-// with 2000 the window is reached only by those, whereas 500 and 1000 also
-// restarted (and slowed) healthy energies.
-constexpr int kStallIters = 2000;
 
 // Convergence test on the recurrence residual, then beta and rho.
 __global__ void k_sse_beta(SseArgs a, double rtol, int maxit) {
@@ -493,7 +480,7 @@ __global__ void k_sse_true(SseArgs a, double rtol, int maxit) {
   sc.fb_pending = 0;
   if (rr <= rtol * rtol * sc.ff) {
     sc.state = kDone;
-  } else if (sc.iters >= maxit || (!fb && sc.restarts >= 8)) {
+  } else if (sc.iters >= maxit || (!fb && sc.restarts >= kMaxRestarts)) {
     sc.state = kMaxit;
   } else {
     sc.rr = rr;
@@ -668,6 +655,7 @@ static SseSizes sse_sizes(const Plan& p) {
 static size_t r256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t sse_solver_bytes(const Plan& p, int nE) {
+  if (p.prob.ndim == 1) return sse1_solver_bytes(nE);
   const SseSizes z = sse_sizes(p);
   return 5 * r256(z.bytes_vec * nE) + r256(z.bytes_vec) + r256(sizeof(double) * nE * z.nbr) +
          2 * r256(sizeof(cx<double>) * nE * z.nbr) + r256(sizeof(cx<double>) * nE * z.nbc) +
@@ -752,8 +740,13 @@ static SseLauncher launcher_of(const Plan& p) {
 }
 
 static sofft_status sse_check_plan(const Plan& p) {
-  if ((p.prob.ndim != 2 && p.prob.ndim != 3) || p.prob.dtype != SOFFT_C128) {
-    set_error("the stationary solver works on 2D and 3D complex128 plans");
+  if (p.prob.dtype != SOFFT_C128) {
+    set_error("the stationary solver works on complex128 plans");
+    return SOFFT_EUNSUPPORTED;
+  }
+  if (p.prob.ndim == 1) {
+    if (sse1_supported(p.ax[0].n)) return SOFFT_OK;
+    set_error("no 1D stationary-solver kernel for n = " + std::to_string(p.ax[0].n));
     return SOFFT_EUNSUPPORTED;
   }
   if (!launcher_of(p)) {
@@ -798,10 +791,12 @@ sofft_status sse_solve(Plan& p, const void* f, int f_per_energy, const double* E
                        int patience, const double* eta_host, int banded) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
-  if (p.prob.ndim == 3 && lp) {
+  if (p.prob.ndim != 2 && lp) {
     set_error("the learned correction works on 2D grids");
     return SOFFT_EUNSUPPORTED;
   }
+  if (p.prob.ndim == 1)
+    return sse1_run(p, 0, f, f_per_energy, E_host, nE, field, x_out, rtol, maxit, stats, s, eta_host, banded);
   SseArgs a{};
   if ((st = sse_prepare(p, nE, field, a, s)) != SOFFT_OK) return st;
   a.learned = lp ? 1 : 0;
@@ -954,6 +949,9 @@ sofft_status sse_apply(Plan& p, int op, const void* v, void* w, double E, double
                        int banded) {
   sofft_status st = sse_check_plan(p);
   if (st != SOFFT_OK) return st;
+  if (p.prob.ndim == 1)
+    return sse1_run(p, op == 0 ? 1 : 2, v, 0, &E, 1, field, w, 0.0, 0, nullptr, s, eta != 0.0 ? &eta : nullptr,
+                    banded);
   SseArgs a{};
   if ((st = sse_prepare(p, 1, field, a, s)) != SOFFT_OK) return st;
   SOFFT_HIP_TRY(hipMemcpyAsync(a.E_dev, &E, sizeof(double), hipMemcpyHostToDevice, s));

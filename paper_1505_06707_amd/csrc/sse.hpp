@@ -15,6 +15,15 @@ enum CocgState : int {
   kBreakdown = 4,  // rho or p^T A p vanished twice in a row
 };
 
+// Plain COCG restarts from the true residual after this many iterations
+// without a new minimum of ||r||.  On the 512^2 TFECS workload (2000-6300
+// iterations per energy) single energies otherwise stalled near 1e-6..1e-5;
+// with 2000 the window is reached only by those, whereas 500 and 1000 also
+// restarted (and slowed) healthy energies.
+constexpr int kStallIters = 2000;
+// Restarts from the true residual after which an energy stops as not converged.
+constexpr int kMaxRestarts = 8;
+
 struct CocgScalars {
   cx<double> rho, alpha, beta;
   double rr, ff, true_res;
@@ -108,6 +117,13 @@ __device__ __forceinline__ cx<double> block_sum(cx<double> v, cx<double>* red) {
   return acc;
 }
 
+__device__ __forceinline__ double cabs2(cx<double> v) { return v.re * v.re + v.im * v.im; }
+
+__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
 // C applied on the strip of a line held in LDS (plain layout): element e's
 // row of C times the line, zero off the strip.
 __device__ __forceinline__ cx<double> c_apply(const LineLDS<double>& L, int e, int n, int j0, int m,
@@ -164,5 +180,13 @@ using SseLauncher = sofft_status (*)(SseKernel, const SseArgs&, int, int, hipStr
 SseLauncher sse3_launcher(int64_t nx, int64_t ny, int64_t nz);
 // Blocks per energy of the 3D x passes (nbr) and z pass (nbc): the partial sums they write.
 void sse3_blocks(int64_t nx, int64_t ny, int64_t nz, int* nbr, int* nbc);
+
+// 1D grids (sse1d.hip): one workgroup per energy runs the whole solve.  mode 0
+// solves; mode 1 writes A f and mode 2 P^-1 f to x_out (one energy).
+size_t sse1_solver_bytes(int nE);
+bool sse1_supported(int64_t n);
+sofft_status sse1_run(Plan& p, int mode, const void* f, int f_per_energy, const double* E_host, int nE, double field,
+                      void* x_out, double rtol, int maxit, sofft_solve_stats* stats, hipStream_t s,
+                      const double* eta_host, int banded);
 
 }  // namespace sofft

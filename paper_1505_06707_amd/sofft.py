@@ -133,6 +133,7 @@ _SIGS = {
 KERNEL_ROW, KERNEL_COL, KERNEL_1D = 0, 1, 2
 KERNEL_SSE_ROW_MV, KERNEL_SSE_COL_MV, KERNEL_SSE_ROW_UPD, KERNEL_SSE_COL_PREC, KERNEL_SSE_ROW_PREC = 3, 4, 5, 6, 7
 KERNEL_3D_KINETIC, KERNEL_3D_STRIP = 8, 9
+KERNEL_SSE_1D = 10
 
 
 def exported_symbols():
