@@ -481,10 +481,11 @@ __global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const
   for (int s = 0; s < P; ++s) v[s] = widen(a.psi[t + TPL * s]);
 #pragma unroll
   for (int s = 0; s < P; ++s) kf[s] = kin_half[t + TPL * s];
-  fft2<X, N, -1>(v, L, Lb, t, a.tw);
+  constexpr bool swz = fft2_swizzle<N>();   // the line is contiguous in LDS
+  fft2<X, N, -1, false, swz>(v, L, Lb, t, a.tw);
 #pragma unroll
   for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kf[s]);
-  fft2<X, N, +1>(v, L, Lb, t, a.tw);
+  fft2<X, N, +1, false, swz>(v, L, Lb, t, a.tw);
   for (int64_t n = 0; n < nsteps; ++n) {
     const double fh = (a.f_mid ? a.f_mid[n] : 0.0) * a.ht;
     pot_cn_pot<T, N>(v, L, t, a, [&](int e) {
@@ -494,10 +495,10 @@ __global__ void __launch_bounds__(N / Shape<N>::P) k_tdse1d(PassArgs<T> a, const
     const cx<double>* kin = n + 1 == nsteps ? kin_half : kin_full;
 #pragma unroll
     for (int s = 0; s < P; ++s) kf[s] = kin[t + TPL * s];
-    fft2<X, N, -1>(v, L, Lb, t, a.tw);
+    fft2<X, N, -1, false, swz>(v, L, Lb, t, a.tw);
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kf[s]);
-    fft2<X, N, +1>(v, L, Lb, t, a.tw);
+    fft2<X, N, +1, false, swz>(v, L, Lb, t, a.tw);
   }
 #pragma unroll
   for (int s = 0; s < P; ++s) a.psi[t + TPL * s] = narrow<T>(v[s]);
