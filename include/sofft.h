@@ -216,9 +216,10 @@ typedef struct {
  * iterations (stagnation in finite precision); stats.restarts counts both,
  * and an energy stops as SOFFT_NOT_CONVERGED after 8 restarts.
  *   f       device, [n_y][n_x] (f_per_energy = 0, shared) or [nE][n_y][n_x]
- *           ([n_z][n_y][n_x] and [nE][n_z][n_y][n_x] on 3D plans)
+ *           ([n_x] and [nE][n_x] on 1D plans, [n_z][n_y][n_x] and
+ *           [nE][n_z][n_y][n_x] on 3D plans)
  *   E_host  host, nE energies
- *   x_out   device, [nE][n_y][n_x] ([nE][n_z][n_y][n_x] in 3D), written
+ *   x_out   device, [nE][n_y][n_x] ([nE][n_x] in 1D, [nE][n_z][n_y][n_x] in 3D), written
  *   stats   host, nE entries (may be NULL)
  * Complex128 plans of 1, 2 or 3 dimensions.  In 3D (Sec. III: the FFT
  * preconditioner carries over to the many-dimensional case)
@@ -236,7 +237,7 @@ sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_ener
 
 /* One application of the stationary matrix (op 0: w = A v, Eq. linsys) or of
  * the FFT preconditioner (op 1: w = P^-1 v, Eq. PreconFFT) at energy E, on
- * device vectors [n_y][n_x] ([n_z][n_y][n_x] on 3D plans).  Needs the workspace of one energy
+ * device vectors [n_y][n_x] ([n_x] on 1D plans, [n_z][n_y][n_x] on 3D plans).  Needs the workspace of one energy
  * (sofft_workspace_size(plan, 1)).  Asynchronous on the stream. */
 sofft_status sofft_sse_apply(sofft_plan* plan, int32_t op, const void* v, void* w, double E, double field,
                              void* stream);

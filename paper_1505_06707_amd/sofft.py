@@ -336,7 +336,8 @@ class Plan:
                   banded=False):
         """Solve (H - E_j) x_j = f for every energy; returns (x, stats, status).
 
-        f: complex128 device tensor [ny][nx] (shared) or [nE][ny][nx].
+        f: complex128 device tensor of the grid's shape, self.shape ([nx],
+        [ny][nx] or [nz][ny][nx]), shared by all energies, or [nE] + that shape.
         eta: None (the preconditioner of Eq. PreconFFT) or per-energy shifts of
         its divisor (sofft_sse_solve_shifted).  banded: the preconditioner of
         Eq. PreconFFT_ECS (sofft_sse_solve_banded)."""
