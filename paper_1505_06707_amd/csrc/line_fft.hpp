@@ -120,13 +120,28 @@ template <int N>
 __device__ __forceinline__ void stage_twiddle_load(cx<double> (&w)[Shape<N>::P / Shape<N>::RR][Shape<N>::RR - 1],
                                                    const cx<double>* __restrict__ tws, int t, int sh) {
   constexpr int P = Shape<N>::P, R0 = Shape<N>::R0, RR = Shape<N>::RR, TPL = N / P, B = P / RR;
-  const int ns = R0 << sh;
+  if constexpr ((R0 & (R0 - 1)) == 0) {
+    // Power-of-two lines: j mod ns by a mask, and unsigned 32-bit byte offsets
+    // from the table base, so the loads take the scalar-base form without
+    // 64-bit address arithmetic per lane.
+    const unsigned ns = unsigned(R0) << sh;
+    const char* base = reinterpret_cast<const char*>(tws);
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const int j = t + TPL * b;
-    const int k = j - ((j >> sh) / R0) * ns;
+    for (int b = 0; b < B; ++b) {
+      const unsigned k = (unsigned(t) + TPL * b) & (ns - 1);
 #pragma unroll
-    for (int m = 1; m < RR; ++m) w[b][m - 1] = tws[(m - 1) * ns + k];
+      for (int m = 1; m < RR; ++m)
+        w[b][m - 1] = *reinterpret_cast<const cx<double>*>(base + (((m - 1) * ns + k) << 4));
+    }
+  } else {
+    const int ns = R0 << sh;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int j = t + TPL * b;
+      const int k = j - ((j >> sh) / R0) * ns;
+#pragma unroll
+      for (int m = 1; m < RR; ++m) w[b][m - 1] = tws[(m - 1) * ns + k];
+    }
   }
 }
 
