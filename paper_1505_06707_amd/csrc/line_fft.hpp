@@ -291,7 +291,7 @@ __device__ __forceinline__ void fft2(cx<double> (&v)[Shape<N>::P], const LineLDS
   }
   int off = 0;
   bool odd = true;
-  int sh0 = 0;
+  constexpr int sh0 = SWZ ? LR : 0;
   if constexpr (SWZ) {   // the first rolled stage (stride R0), swizzled
     rolled_stage<X, N, SIGN, false, true>(v, Lb, t, w, 0, xw);
     off += (RR - 1) * R0;
@@ -300,9 +300,12 @@ __device__ __forceinline__ void fft2(cx<double> (&v)[Shape<N>::P], const LineLDS
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = widen(Lb[tr + TPL * s]);
     odd = false;
-    sh0 = LR;
   }
-#pragma unroll 1
+  // Unrolled, each stage's stride is a compile-time constant (shifts and LDS
+  // offsets fold into immediates); the longest lines keep one rolled copy,
+  // whose unrolled form spills.
+  constexpr int kStageUnroll = N > 2048 ? 1 : K;
+#pragma unroll kStageUnroll
   for (int sh = sh0; sh < LR * (K - 1); sh += LR) {
     const LineLDS<X>& Lx = odd ? Lb : L;
     rolled_stage<X, N, SIGN, false>(v, Lx, t, w, sh);
