@@ -161,6 +161,29 @@ sofft_status sofft_set_potential(sofft_plan* plan, const void* v0, const double*
  * a2 > 0 unless charge = 0.  Asynchronous on the stream. */
 sofft_status sofft_make_softcore(const sofft_plan* plan, double charge, double a2, void* v0, void* stream);
 
+/* Complex absorbing potentials of Sec. IV, the alternatives to ECS that the
+ * paper compares it with: a potential U_a added to U on a grid that is not
+ * scaled (a plan with contour SOFFT_ECS_OFF, so q = 1 and z = x).  On each
+ * axis, with r_s = R0[axis] (which must lie in (0, L/2) for this call even
+ * though the contour is off), Dx_CS = L/2 - r_s and s = (|x| - r_s)/Dx_CS at
+ * the real node x, U_a = 0 for |x| <= r_s and beyond:
+ *   SOFFT_ABSORBER_CAP   U_a = E_cap [1 - q(x)^2] with q of Eq. qSECS (end
+ *                        angle pi/4): E_cap [1 - exp(i pi s/2)] (Eq. CAP_via_q);
+ *                        param = E_cap (the paper: 2)
+ *   SOFFT_ABSORBER_TFAP  U_a = -i (k_min^2/2) y(s), y(s) = [a s - b s^3
+ *                        + 4/(1-s)^2 - 4/(1+s)^2]/c^2, a = c^3 - 16,
+ *                        b = c^3 - 17, c = 2.622057 (Eqs. TFAP, yTFAP);
+ *                        param = k_min (the paper: 0.25)
+ * On a grid of several dimensions the axis terms are summed.  The call ADDS
+ * U_a to v0 (device, complex128, the plan's grid [n_z][n_y][n_x], caller-owned;
+ * start it from sofft_make_softcore or zeros) and enqueues one kernel on the
+ * stream; pass the result to sofft_set_potential.  The nodes stop half a cell
+ * short of the box edge, so y(s) is finite at every node.  Returns
+ * SOFFT_EINVAL for a NULL plan or v0, an unknown kind, param not finite and
+ * positive, or an R0 outside (0, L/2). */
+typedef enum { SOFFT_ABSORBER_CAP = 0, SOFFT_ABSORBER_TFAP = 1 } sofft_absorber;
+sofft_status sofft_add_absorber(const sofft_plan* plan, int32_t kind, double param, void* v0, void* stream);
+
 /* Advance psi (device, in place, n_x [* n_y] elements) by nsteps split-operator
  * steps of length dt (Sec. II):
  *   psi <- F^-1 e^{-iK dt/2} F  e^{-iU dt/2}  e^{-iC dt}  e^{-iU dt/2}  F^-1 e^{-iK dt/2} F  psi

@@ -181,6 +181,7 @@ sofft_status launch_softcore_3d(const Plan& p, double charge, double a2, void* o
 sofft_status launch_norm2(Plan& p, const void* psi, double* out, hipStream_t s);
 // V0 = -charge / sqrt(sum z^2 + a2) on the plan's grid into out (complex, [ny][nx]).
 sofft_status launch_softcore(const Plan& p, double charge, double a2, void* out, hipStream_t s);
+sofft_status launch_absorber(const Plan& p, int kind, double param, void* v0, hipStream_t s);
 sofft_status launch_pass(Plan& p, const PassRequest& rq, hipStream_t s);
 // Build or refresh the potential-phase table of a plan for dt (enqueued on s).
 sofft_status ensure_vphase(Plan& p, double dt, hipStream_t s, bool* changed,

@@ -622,6 +622,21 @@ sofft_status sofft_make_softcore(const sofft_plan* plan, double charge, double a
   return launch_softcore(*plan, charge, a2, v0, reinterpret_cast<hipStream_t>(stream));
 }
 
+sofft_status sofft_add_absorber(const sofft_plan* plan, int32_t kind, double param, void* v0, void* stream) {
+  if (!plan || !v0 || (kind != SOFFT_ABSORBER_CAP && kind != SOFFT_ABSORBER_TFAP) || !std::isfinite(param) ||
+      !(param > 0)) {
+    set_error("bad argument to sofft_add_absorber");
+    return SOFFT_EINVAL;
+  }
+  const sofft_problem& p = plan->prob;
+  for (int d = 0; d < p.ndim; ++d)
+    if (!(p.R0[d] > 0 && p.R0[d] < p.L[d] / 2)) {
+      set_error("the absorber needs 0 < R0 < L/2 on every axis");
+      return SOFFT_EINVAL;
+    }
+  return launch_absorber(*plan, kind, param, v0, reinterpret_cast<hipStream_t>(stream));
+}
+
 sofft_status sofft_sse_solve(sofft_plan* plan, const void* f, int32_t f_per_energy, const double* E_host,
                              int32_t nE, double field, void* x_out, double rtol, int32_t maxit,
                              sofft_solve_stats* stats, void* stream) {

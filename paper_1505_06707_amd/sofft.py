@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libsofft.so")
 
 C128, C64 = 0, 1
 SECS, SHARP, ECS_OFF, TFECS = 0, 1, 2, 3
+ABSORBER_CAP, ABSORBER_TFAP = 0, 1
 
 _STATUS = {0: "SOFFT_OK", -1: "SOFFT_EINVAL", -2: "SOFFT_EUNSUPPORTED", -3: "SOFFT_EHIP",
            -4: "SOFFT_ENOMEM", -5: "SOFFT_EWORKSPACE", 1: "SOFFT_NOT_CONVERGED", 2: "SOFFT_BREAKDOWN"}
@@ -71,6 +72,8 @@ _SIGS = {
     "sofft_set_potential": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sofft_make_softcore": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                            ctypes.c_void_p]),
+    "sofft_add_absorber": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
     "sofft_sse_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_double,
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
@@ -301,6 +304,16 @@ class Plan:
         ptr = _dev_ptr(out, torch.complex128, self.numel, "out")
         _check(lib().sofft_make_softcore(self._h, float(charge), float(a2), ptr, _stream(stream)))
         return out
+
+    def add_absorber(self, kind, param, v0, stream=None):
+        """Add the absorbing potential ``kind`` ("cap": param = E_cap, or
+        "tfap": param = k_min) of Sec. IV to the complex128 device tensor v0
+        on the plan's grid, in place; returns v0."""
+        import torch
+        code = {"cap": ABSORBER_CAP, "tfap": ABSORBER_TFAP}[kind]
+        ptr = _dev_ptr(v0, torch.complex128, self.numel, "v0")
+        _check(lib().sofft_add_absorber(self._h, code, float(param), ptr, _stream(stream)))
+        return v0
 
     def timing(self, enable=True):
         """Enable (clearing the record) or disable per-launch event timing."""
