@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsofft.so")
 
-SOURCES = ["plan.hip", "tdse.hip", "tdse3d.hip", "sse.hip", "sse1d.hip", "sse3d.hip", "batch.hip", "learned.hip", "banded.hip"]
+SOURCES = ["plan.hip", "tdse.hip", "tdse3d.hip", "sse.hip", "sse1d.hip", "sse3d.hip", "batch.hip", "learned.hip", "banded.hip", "absorbers.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

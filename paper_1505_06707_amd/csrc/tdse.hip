@@ -533,54 +533,6 @@ __global__ void __launch_bounds__(256) k_softcore(cx<double>* out, int nx, int n
   out[i] = potential_value(cmul(zx[jx], zx[jx]) + zy2 + cx<double>{a2, 0.0}, charge, 0.0);
 }
 
-// Absorbing potentials of Sec. IV on one axis, at s = (|x| - r_s)/Dx_CS:
-// CAP (Eq. CAP_via_q with the contour of Eq. qSECS, end angle pi/4)
-//   E_cap [1 - exp(i pi s/2)];
-// TFAP (Eqs. TFAP, yTFAP) -i (k_min^2/2) y(s), where the pole terms
-//   4/(1-s)^2 - 4/(1+s)^2 are taken as 16 s/(1-s^2)^2 (the same function,
-//   without the cancellation near s = 0).
-struct AbsorberAxis {
-  const double* x;
-  int n;
-  double r_s, width;
-};
-struct AbsorberArgs {
-  AbsorberAxis ax[3];
-  int ndim, kind;
-  double param;
-};
-
-__device__ __forceinline__ cx<double> absorber_1d(double x, const AbsorberAxis& a, int kind, double param) {
-  const double d = fabs(x) - a.r_s;
-  if (!(d > 0.0)) return {0.0, 0.0};
-  const double s = d / a.width;
-  if (kind == SOFFT_ABSORBER_CAP) {
-    double sn, cs;
-    sincospi(0.5 * s, &sn, &cs);
-    return {param * (1.0 - cs), -param * sn};
-  }
-  constexpr double c = 2.622057, c2 = c * c, c3 = c2 * c;
-  const double u = 1.0 - s * s;
-  const double y = ((c3 - 16.0) * s - (c3 - 17.0) * s * s * s + 16.0 * s / (u * u)) / c2;
-  return {0.0, -0.5 * param * param * y};
-}
-
-// v0 += sum over axes of the absorber of its axis, on the [nz][ny][nx] grid.
-__global__ void __launch_bounds__(256) k_add_absorber(cx<double>* v0, AbsorberArgs a) {
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  size_t total = 1;
-  for (int d = 0; d < a.ndim; ++d) total *= size_t(a.ax[d].n);
-  if (i >= total) return;
-  cx<double> u{0.0, 0.0};
-  size_t r = i;
-  for (int d = 0; d < a.ndim; ++d) {
-    const int j = int(r % size_t(a.ax[d].n));
-    r /= size_t(a.ax[d].n);
-    u = u + absorber_1d(a.ax[d].x[j], a.ax[d], a.kind, a.param);
-  }
-  v0[i] = v0[i] + u;
-}
-
 __global__ void k_step_add(int64_t* counter, int64_t delta, int set) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = set ? delta : *counter + delta;
 }
@@ -1105,22 +1057,6 @@ sofft_status launch_softcore(const Plan& p, double charge, double a2, void* out,
   k_softcore<<<unsigned((n + 255) / 256), 256, 0, s>>>(
       static_cast<cx<double>*>(out), nx, ny, static_cast<const cx<double>*>(p.ax[0].z_dev.p),
       p.prob.ndim == 2 ? static_cast<const cx<double>*>(p.ax[1].z_dev.p) : nullptr, charge, a2);
-  SOFFT_HIP_TRY(hipGetLastError());
-  return SOFFT_OK;
-}
-
-sofft_status launch_absorber(const Plan& p, int kind, double param, void* v0, hipStream_t s) {
-  AbsorberArgs a{};
-  a.ndim = p.prob.ndim;
-  a.kind = kind;
-  a.param = param;
-  size_t total = 1;
-  for (int d = 0; d < a.ndim; ++d) {
-    const Axis& A = p.ax[d];
-    a.ax[d] = {static_cast<const double*>(A.x_dev.p), int(A.n), p.prob.R0[d], p.prob.L[d] / 2 - p.prob.R0[d]};
-    total *= size_t(A.n);
-  }
-  k_add_absorber<<<unsigned((total + 255) / 256), 256, 0, s>>>(static_cast<cx<double>*>(v0), a);
   SOFFT_HIP_TRY(hipGetLastError());
   return SOFFT_OK;
 }
