@@ -71,6 +71,7 @@ def test_null_arguments_are_rejected():
     assert L.sofft_norm2(None, None, None, None) == -1
     assert L.sofft_set_potential(None, None, None) == -1
     assert L.sofft_make_softcore(None, 1.0, 1.0, None, None) == -1
+    assert L.sofft_add_absorber(None, sofft.ABSORBER_TFAP, 0.25, None, None) == -1
 
 
 def test_workspace_calls_reject_null_arguments():
