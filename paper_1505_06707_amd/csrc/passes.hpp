@@ -69,12 +69,19 @@ __device__ __forceinline__ void wave_sync() {
 // wavefront); k wavefronts share the line, wavefront q taking groups q, q + k,
 // ... (the host keeps 2D strips at m <= 256, so at most 4 groups).  With k > 1
 // the levels are separated by block barriers, with k = 1 by wavefront ones.
+// G bounds the groups one wavefront takes (at most ceil(W/k) of the W groups
+// a strip of a line of N points can hold); callers that know k at compile time
+// pass it, which keeps the other groups' coefficients out of the registers.
 constexpr int kPcrGroups = 4;
 __host__ __device__ __forceinline__ int cn_result(int m, int levels) { return (levels & 1) ? 0 : m; }
+template <int N>
+__host__ __device__ constexpr int pcr_groups() {
+  return N / 128 > 0 ? (N / 128 < kPcrGroups ? N / 128 : kPcrGroups) : 1;
+}
 
-template <typename T, int N, typename X>
+template <typename T, int N, typename X, int G = pcr_groups<N>()>
 __device__ __forceinline__ void pcr_line(const LineLDS<X>& Lw, int lane, int q, int k, const PassArgs<T>& a) {
-  constexpr int W = N / 128 > 0 ? (N / 128 < kPcrGroups ? N / 128 : kPcrGroups) : 1;
+  constexpr int W = G;
   const int m = a.m, levels = a.levels;
   const int ngroups = (m + 63) >> 6;
   int src = 0, dst = m;

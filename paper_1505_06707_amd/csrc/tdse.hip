@@ -107,15 +107,16 @@ __device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const L
 }
 
 // Blocks of the 2D passes have 1024 threads (four 1024-point lines, or more
-// shorter ones) for P = 4 shapes, which then keep <= 128 VGPRs (4 waves per
-// SIMD), and at most 512 threads for P = 12 shapes (radix 3), which need more
-// registers: 168 VGPRs at 3 waves per SIMD (a few spills, measured faster
-// for batches of such lines than 2 waves without spills).
+// shorter ones) for P = 4 shapes, which then keep <= 96 VGPRs (5 waves per
+// SIMD; 6 spilled and measured slower, 4 measured 5% slower), and at most 512
+// threads for P = 12 shapes (radix 3), which need more registers: 168 VGPRs
+// at 3 waves per SIMD (a few spills, measured faster for batches of such
+// lines than 2 waves without spills).
 constexpr int kRowThreads = 1024;
 constexpr int kColThreads = 1024;
 template <int N>
 constexpr int min_waves_per_simd() {
-  return Shape<N>::P == 4 ? 4 : 3;
+  return Shape<N>::P == 4 ? 5 : 3;
 }
 // Threads per block: THREADS (P = 12 shapes at most 512, so that two waves
 // per SIMD leave them 256 VGPRs), and at least one whole line.
@@ -151,7 +152,13 @@ template <typename T, int N, typename LineOf>
 __device__ __forceinline__ void cn_block(int lpb, const PassArgs<T>& a, LineOf line_of) {
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;   // whole wavefronts
-  if (nw >= lpb && nw % lpb == 0) {
+  constexpr int TPL = N / Shape<N>::P;
+  if constexpr (TPL >= 64) {
+    // blocks of whole lines (lpb = blockDim.x / TPL): the TPL/64 wavefronts of
+    // a line share its strip, each taking at most ceil(W k / TPL) groups
+    constexpr int k = TPL / 64, W = pcr_groups<N>();
+    pcr_line<T, N, xch_t<T>, (W + k - 1) / k>(line_of(w / k), lane, w % k, k, a);
+  } else if (nw >= lpb && nw % lpb == 0) {
     const int k = nw / lpb;
     pcr_line<T, N>(line_of(w / k), lane, w % k, k, a);
   } else {
@@ -218,11 +225,9 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
     cx<double> v[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) v[s] = widen(gload(line + t + TPL * s));
-    // kinetic factors, static potential phases and x of the field term: with
-    // P = 4 fetched before the transforms (latency hidden behind them); the
-    // P = 12 shapes fetch them where they are used, which keeps 120 VGPRs
-    // free during the transforms.
-    constexpr bool early = P == 4;
+    // kinetic factors, static potential phases and x of the field term are
+    // fetched where they are used: held across the transforms they cost the
+    // registers of a fifth wave per SIMD (P = 4) or 120 VGPRs (P = 12).
     cx<double> kin[P];
     auto load_kin = [&]() {
 #pragma unroll
@@ -255,10 +260,6 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
         f = fm ? fm[step] : 0.0;
       }
     };
-    if constexpr (early) {
-      load_kin();
-      load_pot();
-    }
     // A row of TPL <= 64 threads (TPL dividing 64) lies within one wavefront:
     // its exchanges then need wavefront barriers only, and the rows of a
     // block progress independently.
@@ -267,18 +268,18 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
       const LineLDS<X> Lb{lines, l * a.lds_line + fft_lds_elems<N>(), 1};
       constexpr bool swz = fft2_swizzle<N>();   // rows are contiguous in LDS
       fft2<X, N, -1, wave_rows, swz>(v, L, Lb, t, a.tw);
-      if constexpr (!early) load_kin();
+      load_kin();
 #pragma unroll
       for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
       fft2<X, N, +1, wave_rows, swz>(v, L, Lb, t, a.tw);
     } else {
       fft<X, N, -1, wave_rows>(v, L, t, a.tw);
-      if constexpr (!early) load_kin();
+      load_kin();
 #pragma unroll
       for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
       fft<X, N, +1, wave_rows>(v, L, t, a.tw);
     }
-    if constexpr (!early) load_pot();
+    load_pot();
     if (a.do_pot) {
       // Rows outside the y-strip get both potential half-steps here (C_y is the
       // identity on them); rows on it get the first, the column pass the second.
