@@ -439,17 +439,26 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
     }
 #pragma unroll
     for (int s = SE; s < P - SE; ++s) v[s] = widen(raw[s]);
+    // the kinetic factors: for P = 4 fetched before the transforms (latency
+    // hidden behind them); the P = 12 shapes fetch them where they are used,
+    // which keeps their column pass free of spills
     cx<double> kin[P];
+    auto load_kin = [&]() {
 #pragma unroll
-    for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
+      for (int s = 0; s < P; ++s) kin[s] = a.kin[t + TPL * s];
+    };
+    constexpr bool early_kin = P == 4;
+    if constexpr (early_kin) load_kin();
     if constexpr (fft_buffers<N, X>() == 2) {
       const LineLDS<X> Lb{lines, c + fft_lds_elems<N>() * lpb, lpb};
       fft2<X, N, -1>(v, L, Lb, t, a.tw);
+      if constexpr (!early_kin) load_kin();
 #pragma unroll
       for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
       fft2<X, N, +1>(v, L, Lb, t, a.tw);
     } else {
       fft<X, N, -1>(v, L, t, a.tw);
+      if constexpr (!early_kin) load_kin();
 #pragma unroll
       for (int s = 0; s < P; ++s) v[s] = cmul(v[s], kin[s]);
       fft<X, N, +1>(v, L, t, a.tw);
