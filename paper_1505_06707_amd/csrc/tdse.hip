@@ -106,13 +106,15 @@ __device__ __forceinline__ void pot_cn_pot(cx<double> (&v)[Shape<N>::P], const L
   }
 }
 
-// Blocks of the 2D passes have 1024 threads (four 1024-point lines, or more
-// shorter ones) for P = 4 shapes, which then keep <= 96 VGPRs (5 waves per
-// SIMD; 6 spilled and measured slower, 4 measured 5% slower), and at most 512
-// threads for P = 12 shapes (radix 3), which need more registers: 168 VGPRs
-// at 3 waves per SIMD (a few spills, measured faster for batches of such
-// lines than 2 waves without spills).
-constexpr int kRowThreads = 1024;
+// Row blocks have 256 threads (one 1024-point row, or several shorter ones):
+// independent rows do not wait at each other's barriers, measured 17% faster
+// per row pass than four rows per block.  Column blocks have 1024 threads
+// (four 1024-point columns: 64-byte row segments).  P = 4 shapes keep <= 96
+// VGPRs (5 waves per SIMD; 6 spilled and measured slower, 4 measured 5%
+// slower); P = 12 shapes (radix 3) take at most 512 threads and need more
+// registers: 168 VGPRs at 3 waves per SIMD (a few spills, measured faster for
+// batches of such lines than 2 waves without spills).
+constexpr int kRowThreads = 256;
 constexpr int kColThreads = 1024;
 template <int N>
 constexpr int min_waves_per_simd() {
@@ -198,6 +200,17 @@ __device__ __forceinline__ void run_tiles(int ntiles, Body& body) {
   }
 }
 
+// One-row blocks are assigned so that each XCD runs groups of 4 consecutive
+// rows (block t runs on XCD t mod 8 and takes row 32 (t/32) + 4 (t mod 8) +
+// (t/8) mod 4): the column pass that follows then reads each XCD's rows in
+// 64-kB runs.  Measured 17% faster per column pass than row t on block t, and
+// 8 to 128 rows per group measured slower.  Blocks of several rows keep the
+// identity map.
+__device__ __forceinline__ int xcd_rows(int tile, int lpb, int nlines, int ntiles) {
+  if (lpb != 1 || (nlines & 31) != 0 || ntiles != nlines) return tile;
+  return 32 * (tile >> 5) + 4 * (tile & 7) + ((tile >> 3) & 3);
+}
+
 // Block LDS layout of the 2D passes: [line 0][line 1]...; a block holds
 // blockDim.x / TPL lines of a.lds_line elements.  FFT twiddles and CN
 // coefficients are read from global memory (they stay in the vector L1).
@@ -216,7 +229,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
   const bool cn = a.do_pot && a.m > 0;
   const int64_t step = pass_step(a);
   auto body = [&](int tile) {
-    const int g = tile * lpb + l;
+    const int g = xcd_rows(tile, lpb, nlines, a.ntiles) * lpb + l;
     const bool live = g < nlines;
     const int gg = live ? g : 0;
     const int run = gg / a.ny, crow = gg - run * a.ny;
@@ -320,9 +333,12 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
   run_tiles<PERSIST>(a.ntiles, body);
 }
 
-// Column blocks are assigned so that the blocks one XCD runs hold adjacent
-// columns (workgroups go round-robin over the 8 XCDs): neighbouring columns
-// share 128-byte lines, which then meet in the same L2.
+// Column blocks are assigned so that blocks of neighbouring columns run on one
+// XCD (workgroups go round-robin over the 8 XCDs): the blocks of 4 columns that
+// share 128-byte lines then meet in the same L2.  A single grid takes pairs of
+// adjacent blocks per XCD slot, measured faster than one block per slot (17%
+// per step) and than contiguous bands of columns per XCD (2%); batches keep
+// the bands (pairs measured 6% slower there).
 // Slots (s of element t + TPL s) of a column that can hold y-strip nodes: the
 // strip is symmetric and holds at most half of the nodes, so at most N/4 per
 // side, i.e. one slot per side for P = 4 and three for P = 12.
@@ -332,9 +348,9 @@ __host__ __device__ constexpr int col_edge_slots() { return Shape<N>::P == 4 ? 1
 template <int P, int SE>
 __device__ __forceinline__ constexpr int edge_slot(int k) { return k < SE ? k : P - 2 * SE + k; }
 
-__device__ __forceinline__ int xcd_block(int b, int nblk) {
-  if (nblk % 8 != 0) return b;
-  return (b % 8) * (nblk / 8) + b / 8;
+__device__ __forceinline__ int xcd_block(int b, int nblk, bool single) {
+  if (single) return nblk % 16 != 0 ? b : 16 * (b >> 4) + 2 * (b & 7) + ((b >> 3) & 1);
+  return nblk % 8 != 0 ? b : (b % 8) * (nblk / 8) + b / 8;
 }
 
 template <typename T, int N, bool PERSIST, bool UP = false>
@@ -351,7 +367,7 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
   const bool cn = a.do_pot && a.m > 0;
   const int64_t step = pass_step(a);
   auto body = [&](int tile) {
-    const int g = xcd_block(tile, a.ntiles) * lpb + c;
+    const int g = xcd_block(tile, a.ntiles, a.runs == nullptr) * lpb + c;
     const bool live = g < nlines;
     const int gg = live ? g : 0;
     const int run = gg / a.nx, ccol = gg - run * a.nx;
