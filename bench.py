@@ -40,9 +40,10 @@ def measured_traffic(kernel):
     srcs = [os.path.join(ROOT, "paper_1505_06707_amd", "csrc", n)
             for n in ("tdse.hip", "passes.hpp", "line_fft.hpp", "potential.hpp", "cx.hpp")]
     sha = hashlib.sha256(b"".join(open(p, "rb").read() for p in srcs)).hexdigest()
-    if rec.get("kernel") != kernel or rec.get("source_sha256") != sha:
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None or rec.get("source_sha256") != sha:
         return None
-    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024
+    return (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024
 
 
 def log(msg):

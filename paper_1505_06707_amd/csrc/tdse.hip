@@ -200,15 +200,17 @@ __device__ __forceinline__ void run_tiles(int ntiles, Body& body) {
   }
 }
 
-// One-row blocks are assigned so that each XCD runs groups of 4 consecutive
-// rows (block t runs on XCD t mod 8 and takes row 32 (t/32) + 4 (t mod 8) +
-// (t/8) mod 4): the column pass that follows then reads each XCD's rows in
-// 64-kB runs.  Measured 17% faster per column pass than row t on block t, and
-// 8 to 128 rows per group measured slower.  Blocks of several rows keep the
-// identity map.
+// One-row blocks are assigned so that each XCD runs groups of RG consecutive
+// rows, 64 KiB of state (block t runs on XCD t mod 8 and takes row
+// 8 RG floor(t / 8 RG) + RG (t mod 8) + floor(t/8) mod RG): the column pass that
+// follows then reads each XCD's rows in 64-KiB runs.  At 1024^2 complex128
+// (RG = 4) this measured 17% faster per column pass than row t on block t;
+// 8 to 128 rows per group measured slower there.  Blocks of several rows
+// keep the identity map.
+template <int RG>
 __device__ __forceinline__ int xcd_rows(int tile, int lpb, int nlines, int ntiles) {
-  if (lpb != 1 || (nlines & 31) != 0 || ntiles != nlines) return tile;
-  return 32 * (tile >> 5) + 4 * (tile & 7) + ((tile >> 3) & 3);
+  if (lpb != 1 || nlines % (8 * RG) != 0 || ntiles != nlines) return tile;
+  return 8 * RG * (tile / (8 * RG)) + RG * (tile & 7) + (tile >> 3) % RG;
 }
 
 // Block LDS layout of the 2D passes: [line 0][line 1]...; a block holds
@@ -229,7 +231,8 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
   const bool cn = a.do_pot && a.m > 0;
   const int64_t step = pass_step(a);
   auto body = [&](int tile) {
-    const int g = xcd_rows(tile, lpb, nlines, a.ntiles) * lpb + l;
+    constexpr int RG = (65536 / int(N * sizeof(cx<T>))) > 1 ? (65536 / int(N * sizeof(cx<T>))) : 1;
+    const int g = xcd_rows<RG>(tile, lpb, nlines, a.ntiles) * lpb + l;
     const bool live = g < nlines;
     const int gg = live ? g : 0;
     const int run = gg / a.ny, crow = gg - run * a.ny;
@@ -334,22 +337,15 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
 }
 
 // Column blocks are assigned so that blocks of neighbouring columns run on one
-// XCD (workgroups go round-robin over the 8 XCDs): the blocks of 4 columns that
-// share 128-byte lines then meet in the same L2.  A single grid takes pairs of
-// adjacent blocks per XCD slot, measured faster than one block per slot (17%
-// per step) and than contiguous bands of columns per XCD (2%); batches keep
-// the bands (pairs measured 6% slower there).
-// Slots (s of element t + TPL s) of a column that can hold y-strip nodes: the
-// strip is symmetric and holds at most half of the nodes, so at most N/4 per
-// side, i.e. one slot per side for P = 4 and three for P = 12.
-template <int N>
-__host__ __device__ constexpr int col_edge_slots() { return Shape<N>::P == 4 ? 1 : 3; }
-// k-th edge slot, k < 2 SE: 0 .. SE-1, then P-SE .. P-1.
-template <int P, int SE>
-__device__ __forceinline__ constexpr int edge_slot(int k) { return k < SE ? k : P - 2 * SE + k; }
-
-__device__ __forceinline__ int xcd_block(int b, int nblk, bool single) {
-  if (single) return nblk % 16 != 0 ? b : 16 * (b >> 4) + 2 * (b & 7) + ((b >> 3) & 1);
+// XCD (workgroups go round-robin over the 8 XCDs): the cg blocks whose columns
+// share 128-byte lines then meet in the same L2.  A single grid takes groups
+// of cg adjacent blocks per XCD slot (cg = 2 for 4 complex128 columns, 4 for
+// complex64), measured faster than one block per slot (17% per step at 1024^2
+// complex128) and than contiguous bands of columns per XCD (2%); at complex64,
+// cg = 4 with RG = 8 measured 10% faster than cg = 2 with RG = 4.  Batches
+// keep the bands (the groups measured 6% slower there).
+__device__ __forceinline__ int xcd_block(int b, int nblk, bool single, int cg) {
+  if (single) return nblk % (8 * cg) != 0 ? b : 8 * cg * (b / (8 * cg)) + cg * (b & 7) + (b >> 3) % cg;
   return nblk % 8 != 0 ? b : (b % 8) * (nblk / 8) + b / 8;
 }
 
@@ -367,7 +363,8 @@ __global__ void __launch_bounds__((kernel_threads<N, kColThreads, PERSIST>()), (
   const bool cn = a.do_pot && a.m > 0;
   const int64_t step = pass_step(a);
   auto body = [&](int tile) {
-    const int g = xcd_block(tile, a.ntiles, a.runs == nullptr) * lpb + c;
+    const int cg = max(1, 128 / (lpb * int(sizeof(cx<T>))));
+    const int g = xcd_block(tile, a.ntiles, a.runs == nullptr, cg) * lpb + c;
     const bool live = g < nlines;
     const int gg = live ? g : 0;
     const int run = gg / a.nx, ccol = gg - run * a.nx;
