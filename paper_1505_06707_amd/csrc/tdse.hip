@@ -344,6 +344,15 @@ __global__ void __launch_bounds__((kernel_threads<N, kRowThreads, PERSIST>()), (
 // complex128) and than contiguous bands of columns per XCD (2%); at complex64,
 // cg = 4 with RG = 8 measured 10% faster than cg = 2 with RG = 4.  Batches
 // keep the bands (the groups measured 6% slower there).
+// Slots (s of element t + TPL s) of a column that can hold y-strip nodes: the
+// strip is symmetric and holds at most half of the nodes, so at most N/4 per
+// side, i.e. one slot per side for P = 4 and three for P = 12.
+template <int N>
+__host__ __device__ constexpr int col_edge_slots() { return Shape<N>::P == 4 ? 1 : 3; }
+// k-th edge slot, k < 2 SE: 0 .. SE-1, then P-SE .. P-1.
+template <int P, int SE>
+__device__ __forceinline__ constexpr int edge_slot(int k) { return k < SE ? k : P - 2 * SE + k; }
+
 __device__ __forceinline__ int xcd_block(int b, int nblk, bool single, int cg) {
   if (single) return nblk % (8 * cg) != 0 ? b : 8 * cg * (b / (8 * cg)) + cg * (b & 7) + (b >> 3) % cg;
   return nblk % 8 != 0 ? b : (b % 8) * (nblk / 8) + b / 8;
