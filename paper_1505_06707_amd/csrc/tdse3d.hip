@@ -70,7 +70,13 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_kinetic(Pass3<T> a) {
     c = threadIdx.x % LPB;
     t = threadIdx.x / LPB;
   }
-  const int g = blockIdx.x * LPB + c;
+  // Each XCD takes one contiguous band of the pass's lines (workgroups go
+  // round-robin over the 8 XCDs): measured 2.5% (complex128) and 4%
+  // (complex64) faster per 256^3 step than block b on lines 8b..8b+7, and
+  // faster than groups of 2 or 4 blocks per XCD slot.
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int bb = nb % 8 ? b : (b % 8) * (nb / 8) + b / 8;
+  const int g = bb * LPB + c;
   const bool live = g < a.nlines;
   int lx, ly, lz;
   size_t ld;
