@@ -53,7 +53,11 @@ __global__ void __launch_bounds__(k3_threads<N>()) k3_sse(SseArgs a, int want, i
     t = threadIdx.x / LPB;
   }
   const int nlines = AXIS == 0 ? a.ny * a.nz : (AXIS == 1 ? a.nx * a.nz : a.nx * a.ny);
-  const int g = blockIdx.x * LPB + c;
+  // one contiguous band of lines per XCD (workgroups go round-robin over the
+  // 8 XCDs): measured 5.5% faster per energy-iteration at 128^3 than block b
+  // on lines LPB b ...; the block partial sums keep their block order
+  const int nbk = gridDim.x, bk = blockIdx.x;
+  const int g = (nbk % 8 ? bk : (bk % 8) * (nbk / 8) + bk / 8) * LPB + c;
   const bool live = g < nlines;
   int lx, ly, lz;
   size_t ld;

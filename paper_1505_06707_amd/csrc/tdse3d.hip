@@ -143,7 +143,8 @@ __global__ void __launch_bounds__(64 * kCnLines) k3_cn(Pass3<T> a, PassArgs<T> c
     c = threadIdx.x % kCnLines;
     r = threadIdx.x / kCnLines;
   }
-  const int g = blockIdx.x * kCnLines + c;
+  const int nbk = gridDim.x, bk = blockIdx.x;   // one band of lines per XCD, as the kinetic passes
+  const int g = (nbk % 8 ? bk : (bk % 8) * (nbk / 8) + bk / 8) * kCnLines + c;
   const bool live = g < a.nlines;
   int lx, ly, lz;
   size_t ld;
