@@ -56,6 +56,15 @@ constexpr int sse_row_bound() { return Shape<N>::P == 4 ? kSseRowThreads : kSseR
 template <int N, bool BANDED>
 constexpr int sse_row_waves() { return Shape<N>::P == 4 ? (BANDED ? kSseBandWaves : kSseRowWaves) : 1; }
 
+// Blocks of the solver's line passes take one contiguous band of lines per
+// XCD (workgroups go round-robin over the 8 XCDs).  Rows: 1-2% per pass
+// against block b on rows lpb b ...; columns: 4% against pairs of adjacent
+// column blocks per XCD slot.  Block partial sums keep their block order.
+__device__ __forceinline__ int xcd_block_sse(int b, int nblk) {
+  if (nblk % 8 != 0) return b;
+  return (b % 8) * (nblk / 8) + b / 8;
+}
+
 // ---------------------------------------------------------------- K1: row part of A v
 template <int N>
 __global__ void __launch_bounds__(sse_row_bound<N>(), (sse_row_waves<N, false>())) k_sse_row_mv(SseArgs a, int want, int mode) {
@@ -67,7 +76,7 @@ __global__ void __launch_bounds__(sse_row_bound<N>(), (sse_row_waves<N, false>()
   cx<double>* lines = reinterpret_cast<cx<double>*>(smem);
   const int lpb = blockDim.x / TPL;
   const int l = threadIdx.x / TPL, t = threadIdx.x - l * TPL;
-  const int row = blockIdx.x * lpb + l;
+  const int row = xcd_block_sse(blockIdx.x, gridDim.x) * lpb + l;
   const bool live = row < a.ny;
   const int crow = live ? row : 0;
   const LineLDS<double> L{lines, l * a.lds_line_x, 1};
@@ -114,10 +123,6 @@ __global__ void __launch_bounds__(sse_row_bound<N>(), (sse_row_waves<N, false>()
   }
 }
 
-__device__ __forceinline__ int xcd_block_sse(int b, int nblk) {
-  if (nblk % 8 != 0) return b;
-  return (b % 8) * (nblk / 8) + b / 8;
-}
 
 // ---------------------------------------------------------------- K2: column part of A v
 // (Holding p in registers for p^T w needs 90 VGPRs.  Reading p again after the
@@ -190,7 +195,7 @@ __global__ void __launch_bounds__(sse_row_bound<N>(), (sse_row_waves<N, BANDED>(
   cx<double>* lines = reinterpret_cast<cx<double>*>(smem);
   const int lpb = blockDim.x / TPL;
   const int l = threadIdx.x / TPL, t = threadIdx.x - l * TPL;
-  const int row = blockIdx.x * lpb + l;
+  const int row = xcd_block_sse(blockIdx.x, gridDim.x) * lpb + l;
   const bool live = row < a.ny;
   const int crow = live ? row : 0;
   const LineLDS<double> L{lines, l * a.lds_line_x, 1};
@@ -298,7 +303,7 @@ __global__ void __launch_bounds__(sse_row_bound<N>(), (sse_row_waves<N, BANDED>(
   cx<double>* lines = reinterpret_cast<cx<double>*>(smem);
   const int lpb = blockDim.x / TPL;
   const int l = threadIdx.x / TPL, t = threadIdx.x - l * TPL;
-  const int row = blockIdx.x * lpb + l;
+  const int row = xcd_block_sse(blockIdx.x, gridDim.x) * lpb + l;
   const bool live = row < a.ny;
   const int crow = live ? row : 0;
   const LineLDS<double> L{lines, l * a.lds_line_x, 1};
