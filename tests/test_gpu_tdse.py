@@ -255,7 +255,11 @@ def test_fp32_1d_error_against_fp64_oracle():
 # (512-, 768- and 1024-point rows) and the column pass's edge-slot CN.
 
 
-STRIP_SHAPES = [(1024, 16), (16, 1024), (512, 32), (32, 512), (768, 48), (48, 768), (384, 64)]
+# (1024, 64) runs the row pass's XCD row groups (one row per block, 64 rows a
+# multiple of 8 groups at complex128 and complex64) and the column pass's
+# column-block groups, as the full-size grid does; (1024, 16) keeps the
+# identity row map.
+STRIP_SHAPES = [(1024, 16), (1024, 64), (16, 1024), (512, 32), (32, 512), (768, 48), (48, 768), (384, 64)]
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
